@@ -1,0 +1,217 @@
+"""CPU oracle for the cube statistics -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  The GPU library never does, and this package never
+imports the GPU library: the two share no code.  Everything here is a plain,
+slow restatement of what the paper (arXiv 1211.4896) defines:
+
+* moments      -- Section 4.2: count, mean and standard deviation of the
+                  non-NULL voxels, plus min/max (known at load, Section 4.1);
+* histogram    -- Section 4.1: a fixed-range N-bin histogram, one visit per
+                  voxel, with the single-precision bin formula
+                  b = min((int)((v - lo) * scale), nbins - 1),
+                  scale = (float)nbins / (hi - lo);
+* median       -- Section 4.3: the exact median, read here as the lower
+                  median (0-based rank floor((n-1)/2) under totalOrder), found
+                  with a library selection (numpy.partition) on a copy;
+* median_sort  -- the same value by qsort, for small inputs;
+* torben       -- Appendix A, Algorithm 1 (Torben Mogensen's method), a second
+                  and independent algorithm for the same value.
+
+NaN is the NULL value and is excluded everywhere.  The C parts live in
+tsa_oracle.c and are built with gcc by ``build()``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "tsa_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+F32, I16 = 0, 1
+
+
+class _Moments(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_uint64), ("nan_count", ctypes.c_uint64), ("mean", ctypes.c_double),
+                ("m2", ctypes.c_double), ("std", ctypes.c_double), ("min", ctypes.c_double),
+                ("max", ctypes.c_double)]
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so (gcc, no fast-math, no FP contraction)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        I64 = ctypes.c_int64
+        lib.oracle_moments.argtypes = [P, ctypes.c_int, I64, I64, I64, P, ctypes.POINTER(_Moments)]
+        lib.oracle_moments.restype = ctypes.c_int
+        lib.oracle_hist_scale.argtypes = [ctypes.c_float, ctypes.c_float, ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_float)]
+        lib.oracle_hist_scale.restype = ctypes.c_int
+        lib.oracle_histogram.argtypes = [P, ctypes.c_int, I64, I64, I64, P, ctypes.c_float, ctypes.c_float,
+                                         ctypes.c_int32, P, P]
+        lib.oracle_histogram.restype = ctypes.c_int
+        lib.oracle_torben_guess.argtypes = [ctypes.c_float, ctypes.c_float]
+        lib.oracle_torben_guess.restype = ctypes.c_float
+        lib.oracle_torben.argtypes = [P, ctypes.c_int, I64, ctypes.POINTER(ctypes.c_float), P, ctypes.c_int]
+        lib.oracle_torben.restype = ctypes.c_int
+        lib.oracle_median_sort.argtypes = [P, ctypes.c_int, I64, I64, I64, P, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_uint64)]
+        lib.oracle_median_sort.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _cube(a: np.ndarray):
+    if a.ndim == 1:
+        a = a.reshape(1, 1, -1)
+    if a.ndim != 3:
+        raise ValueError("cube must be 1-D or (nz, ny, nx)")
+    a = np.ascontiguousarray(a)
+    if a.dtype == np.float32:
+        dt = F32
+    elif a.dtype == np.int16:
+        dt = I16
+    else:
+        raise TypeError("cube dtype must be float32 or int16")
+    nz, ny, nx = a.shape
+    return a, dt, nx, ny, nz
+
+
+def _box(region):
+    if region is None:
+        return None, None
+    b = np.ascontiguousarray(np.asarray(region, dtype=np.int64).reshape(6))
+    return b, b.ctypes.data
+
+
+def moments(a: np.ndarray, region=None) -> dict:
+    """Section 4.2 moments of the non-NaN voxels (plus min/max), in double."""
+    lib = _load()
+    a, dt, nx, ny, nz = _cube(a)
+    b, bp = _box(region)
+    out = _Moments()
+    if lib.oracle_moments(a.ctypes.data, dt, nx, ny, nz, bp, ctypes.byref(out)) != 0:
+        raise ValueError("invalid region or dtype")
+    return {k: getattr(out, k) for k, _ in _Moments._fields_}
+
+
+def hist_scale(lo: float, hi: float, nbins: int) -> float:
+    lib = _load()
+    s = ctypes.c_float()
+    if lib.oracle_hist_scale(lo, hi, nbins, ctypes.byref(s)) != 0:
+        raise ValueError("invalid histogram range or bin count")
+    return s.value
+
+
+def histogram(a: np.ndarray, lo: float, hi: float, nbins: int, region=None):
+    """Section 4.1 histogram: returns (counts uint64[nbins], outliers uint64[2] = below, above)."""
+    lib = _load()
+    a, dt, nx, ny, nz = _cube(a)
+    b, bp = _box(region)
+    counts = np.zeros(nbins, dtype=np.uint64)
+    outl = np.zeros(2, dtype=np.uint64)
+    if lib.oracle_histogram(a.ctypes.data, dt, nx, ny, nz, bp, lo, hi, nbins, counts.ctypes.data,
+                            outl.ctypes.data) != 0:
+        raise ValueError("invalid histogram arguments")
+    return counts, outl
+
+
+def torben_guess(mn: float, mx: float) -> float:
+    return _load().oracle_torben_guess(mn, mx)
+
+
+def torben(a: np.ndarray, trace_cap: int = 0):
+    """Algorithm 1 on the non-NaN values; returns (median float, iterations, trace rows)."""
+    lib = _load()
+    a = np.ascontiguousarray(a).reshape(-1)
+    dt = F32 if a.dtype == np.float32 else I16
+    med = ctypes.c_float()
+    tr = np.zeros((max(trace_cap, 1), 6), dtype=np.float64)
+    it = lib.oracle_torben(a.ctypes.data, dt, a.size, ctypes.byref(med), tr.ctypes.data, trace_cap)
+    if it < 0:
+        raise RuntimeError("Torben iteration cap reached")
+    return med.value, it, tr[:min(it, trace_cap)]
+
+
+def median_sort(a: np.ndarray, region=None):
+    """Lower median by qsort (small inputs): returns (value, count)."""
+    lib = _load()
+    a, dt, nx, ny, nz = _cube(a)
+    b, bp = _box(region)
+    med = ctypes.c_double()
+    cnt = ctypes.c_uint64()
+    if lib.oracle_median_sort(a.ctypes.data, dt, nx, ny, nz, bp, ctypes.byref(med), ctypes.byref(cnt)) != 0:
+        raise ValueError("invalid region or dtype")
+    return med.value, int(cnt.value)
+
+
+def _region_view(a: np.ndarray, region):
+    if a.ndim == 1:
+        a = a.reshape(1, 1, -1)
+    if region is None:
+        return a
+    x0, y0, z0, x1, y1, z1 = (int(v) for v in region)
+    nz, ny, nx = a.shape
+    if not (0 <= x0 < x1 <= nx and 0 <= y0 < y1 <= ny and 0 <= z0 < z1 <= nz):
+        raise ValueError("invalid region")
+    return a[z0:z1, y0:y1, x0:x1]
+
+
+def median(a: np.ndarray, region=None):
+    """Lower median (rank floor((n-1)/2) by totalOrder) of the non-NaN voxels.
+
+    Returns (value, count); value is NaN when count == 0.  Selection is
+    numpy.partition on a copy; numpy orders -0 and +0 as equal, so a zero
+    result takes the sign that totalOrder gives rank k: -0 when more than k
+    values are negative or -0.
+    """
+    v = _region_view(a, region)
+    if v.dtype == np.float32:
+        flat = v.reshape(-1)
+        vals = flat[~np.isnan(flat)]
+    else:
+        vals = v.reshape(-1)
+    n = vals.size
+    if n == 0:
+        return float("nan"), 0
+    k = (n - 1) // 2
+    m = np.partition(vals, k)[k]
+    if vals.dtype == np.float32 and m == 0:
+        n_before = int(np.count_nonzero(vals < 0)) + int(np.count_nonzero((vals == 0) & np.signbit(vals)))
+        m = np.float32(-0.0) if k < n_before else np.float32(0.0)
+    return float(m), n
+
+
+def stats(a: np.ndarray, nbins: int, region=None) -> dict:
+    """The full trio on one cube or region: moments, histogram over the
+    region's own [min, max], and the lower median."""
+    mo = moments(a, region)
+    out = dict(mo)
+    if mo["count"] == 0:
+        out["counts"] = np.zeros(nbins, dtype=np.uint64)
+        out["outliers"] = np.zeros(2, dtype=np.uint64)
+        out["median"] = float("nan")
+        return out
+    lo, hi = np.float32(mo["min"]), np.float32(mo["max"])
+    out["counts"], out["outliers"] = histogram(a, float(lo), float(hi), nbins, region)
+    out["median"], _ = median(a, region)
+    return out
