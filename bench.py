@@ -1,0 +1,238 @@
+#!/usr/bin/env python3
+"""Benchmark of the cube-statistics hot path on one MI355X.
+
+A step is one pass of the whole analysis path of the paper's Section 4 over
+the resident 1024x1024x1280 float32 cube (one GPU's share of a ~0.5 TB cube,
+the paper's load per GPU at 96 GPUs): global moments, the 4096-bin histogram
+over [min, max], and the exact lower median -- one tsa_stats call (two passes
+over the data plus small selection kernels).  Inputs are synthetic and seeded
+(noise + Gaussian sources + NaN slabs) and already resident in HBM when the
+timed region starts.
+
+Prints one JSON line: whole-step throughput in GVoxel/s, the roofline entry of
+the dominant kernel (its duration measured with HIP events on its launch
+stream during the timed steps), the separate-call rates of the histogram and
+the median, and the CPU oracle timed on a bounded sample of the same cube.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5]
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+METRIC = "GVoxel/s + % HBM peak (hist, median); region queries/s batched vs plain, p99"
+KERNEL_SOURCES = ["tsa_device.hpp", "tsa_walk.hpp", "tsa_ops.hpp", "tsa_kernels.hip"]
+
+
+def _src_hash() -> str:
+    h = hashlib.sha256()
+    for s in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1211_4896_amd", "csrc", s), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _counter_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("src_sha256_16") != _src_hash():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def _trace(lib, on: bool, cap: int = 0):
+    st = lib.tsa_trace_enable(1 if on else 0, cap)
+    if st != 0:
+        raise RuntimeError(f"tsa_trace_enable failed ({st})")
+
+
+def _trace_read(lib) -> dict:
+    buf = ctypes.create_string_buffer(1 << 16)
+    n = lib.tsa_trace_read(buf, len(buf))
+    if n < 0:
+        raise RuntimeError(f"tsa_trace_read failed ({n})")
+    return json.loads(buf.value.decode())
+
+
+def _cpu_baseline(host, nbins: int, target_s: float = 12.0) -> dict:
+    """The oracle (plain C + numpy selection, single-threaded) on the first z
+    slices of the same cube: moments, histogram over [min, max], median."""
+    import oracle
+
+    plane = host.shape[1] * host.shape[2]
+    probe = max(1, (1 << 24) // plane)
+    t0 = time.perf_counter()
+    oracle.stats(host[:probe], nbins)
+    t_probe = time.perf_counter() - t0
+    nz = int(min(host.shape[0], max(probe, probe * target_s / max(t_probe, 1e-3))))
+    sample = host[:nz]
+    t0 = time.perf_counter()
+    oracle.stats(sample, nbins)
+    dt = time.perf_counter() - t0
+    nvox = nz * plane
+    return {"value": round(nvox / dt / 1e9, 6), "unit": "GVoxel/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {nz} of {host.shape[0]} z-slices ({nvox} voxels), moments + {nbins}-bin "
+                      f"histogram over [min,max] + lower median, {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ops", action="store_true", help="skip the separate-call measurements")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this path does not shard)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_1211_4896_amd as tsa
+
+    nbins = {"c1": 1024, "c2": 4096}[args.workload]
+    spec = synth.SPECS[args.workload]
+    t0 = time.perf_counter()
+    host, nan = synth.generate(spec)
+    print(f"[bench] generated {spec.nx}x{spec.ny}x{spec.nz} in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+    dev = torch.from_numpy(host).to("cuda:0")
+    torch.cuda.synchronize()
+    N = host.size
+    lib = tsa.capi().lib
+    lib.tsa_trace_enable.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    lib.tsa_trace_read.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
+
+    c = tsa.cube_of(dev)
+    cp = ctypes.byref(c)
+    ws = tsa.workspace(tsa.OP_STATS, dev, None, nbins)
+    out = torch.empty(72, dtype=torch.uint8, device=dev.device)
+    counts = torch.empty(nbins, dtype=torch.int64, device=dev.device)
+    outl = torch.empty(2, dtype=torch.int64, device=dev.device)
+    stream = torch.cuda.current_stream()
+    sh = stream.cuda_stream
+    api = tsa.capi()
+
+    def step():
+        st = api.tsa_stats(cp, None, nbins, out.data_ptr(), counts.data_ptr(), outl.data_ptr(), ws.data_ptr(),
+                           ws.numel(), sh)
+        if st != 0:
+            raise RuntimeError(f"tsa_stats failed: {tsa.status_string(st)}")
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    _trace(lib, True, cap=args.steps * 32)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    ev_ms = e0.elapsed_time(e1) / args.steps
+    kern = _trace_read(lib)
+    _trace(lib, False)
+    res = tsa.results_to_numpy(out)[0]
+    if res["status"] != 0:
+        raise RuntimeError("device status %d" % res["status"])
+
+    ms_per_step = wall_ms
+    value = N / (ms_per_step * 1e-3) / 1e9
+    # dominant kernel by total traced time
+    dom = max(kern.items(), key=lambda kv: kv[1][1])
+    dom_name, (dom_n, dom_tot, dom_min, dom_max) = dom
+    dom_avg_ms = dom_tot / dom_n
+    per_launch_bytes = {"pass_a": 4.0 * N + 8.0 * 4096, "pass_b": 4.0 * N + 8.0 * nbins}.get(dom_name, 4.0 * N)
+    achieved = per_launch_bytes / (dom_avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": _counter_traffic(dom_name, args.workload),
+                "kernel": dom_name, "avg_ms": round(dom_avg_ms, 4),
+                "bytes_per_launch": per_launch_bytes}
+
+    line = {"metric": METRIC, "value": round(value, 2), "unit": "GVoxel/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"{args.workload}: {spec.nx}x{spec.ny}x{spec.nz} float32 cube (seeded noise + "
+                                   f"{spec.n_sources} Gaussian sources + {spec.nan_frac:.1%} NaN slabs); moments + "
+                                   f"{nbins}-bin histogram over [min,max] + exact lower median (tsa_stats)",
+                       "voxels": N, "nbins": nbins, "parallelism": "1 GPU"},
+            "roofline": roofline,
+            "event_ms_per_step": round(ev_ms, 4),
+            "kernels_ms": {k: round(v[1] / v[0], 4) for k, v in kern.items()}}
+
+    if not args.no_ops:
+        line["ops"] = _separate_ops(tsa, api, dev, cp, N, float(res["min"]), float(res["max"]), nbins, sh)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = _cpu_baseline(host, nbins)
+    print(json.dumps(line), flush=True)
+
+
+def _separate_ops(tsa, api, dev, cp, N, lo, hi, nbins, sh, reps: int = 10) -> dict:
+    """Rates of the separate calls: tsa_histogram (one pass), tsa_median
+    (radix selection), tsa_moments (one pass)."""
+    import torch
+
+    ws = tsa.workspace(tsa.OP_HISTOGRAM, dev, None, nbins)
+    out = torch.empty(72, dtype=torch.uint8, device=dev.device)
+    counts = torch.empty(nbins, dtype=torch.int64, device=dev.device)
+    outl = torch.empty(2, dtype=torch.int64, device=dev.device)
+    calls = {
+        "histogram": lambda: api.tsa_histogram(cp, None, lo, hi, nbins, counts.data_ptr(), outl.data_ptr(),
+                                               ws.data_ptr(), ws.numel(), sh),
+        "median": lambda: api.tsa_median(cp, None, out.data_ptr(), ws.data_ptr(), ws.numel(), sh),
+        "moments": lambda: api.tsa_moments(cp, None, out.data_ptr(), ws.data_ptr(), ws.numel(), sh),
+    }
+    res = {}
+    for name, f in calls.items():
+        for _ in range(2):
+            f()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            st = f()
+            if st != 0:
+                raise RuntimeError(f"{name}: {tsa.status_string(st)}")
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        gvs = N / (ms * 1e-3) / 1e9
+        # bytes actually required: one read of the cube per full pass
+        passes = {"histogram": 1, "moments": 1, "median": 2}[name]
+        res[name] = {"ms": round(ms, 4), "gvoxel_s": round(gvs, 2),
+                     "hbm_frac": round(passes * 4.0 * N / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "full_passes": passes}
+    return res
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,187 @@
+/*
+ * tsa.h -- C ABI of the MI355X (gfx950) cube-statistics library (libtsa.so).
+ *
+ * Implements the data-parallel analysis path of Hassan, Fluke, Barnes &
+ * Kilborn, "Tera-scale astronomical data analysis and visualization" (MNRAS,
+ * arXiv 1211.4896), Section 4: global histogram (4.1), global mean and
+ * standard deviation (4.2) and global median (4.3), over 3-D image cubes
+ * held resident in GPU memory, plus batched sub-cube ("local, over small user
+ * defined regions", Section 4 introduction) queries.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Cube layout: dense, x fastest, element (x,y,z) at index x + nx*(y + ny*z)
+ *    (RA, Dec, frequency as in the paper's survey cubes).  Element type float32
+ *    or int16.  The cube pointer is a device pointer; the caller owns it and it
+ *    must stay valid and unmodified until the stream reaches the end of the call.
+ *  - NULL voxels (Section 4: "special handling for the NULL data points") are
+ *    NaN; they are excluded from every statistic and counted in nan_count.
+ *    +-inf are ordinary values.  int16 cubes have no NULL value.
+ *  - Ordering is IEEE-754 totalOrder on non-NaN values (-0 < +0); min, max and
+ *    the median are returned bit-exactly as stored values.
+ *  - A region is a half-open box [x0,x1) x [y0,y1) x [z0,z1) with
+ *    0 <= x0 < x1 <= nx (same for y, z).  Each voxel in it is counted once.
+ *    Passing NULL where a region is accepted means the whole cube.
+ *  - Every compute call is asynchronous on the given HIP stream (NULL = the
+ *    legacy default stream).  Argument errors are detected on the host and
+ *    returned synchronously before anything is enqueued; nothing aborts and no
+ *    exception crosses the ABI.  Data-dependent conditions found on the device
+ *    are reported in tsa_result.status / tsa_result.flags.
+ *  - Device memory for outputs and scratch is owned by the caller.  Scratch
+ *    ("workspace") size comes from tsa_workspace_bytes(); the library never
+ *    allocates or frees device memory in a compute call.
+ *  - Calls on different streams may run concurrently if they use different
+ *    workspaces and outputs.  A workspace must not be shared by two calls that
+ *    can overlap.
+ */
+#ifndef TSA_H
+#define TSA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* hipStream_t without pulling in the HIP headers (same underlying type). */
+typedef struct ihipStream_t* tsa_stream_t;
+
+typedef enum {
+  TSA_OK = 0,
+  TSA_EINVAL = -1,  /* bad argument (null pointer, bad box, bad range, ...) */
+  TSA_ENOMEM = -2,  /* workspace smaller than tsa_workspace_bytes() */
+  TSA_EDEVICE = -3, /* a HIP call or kernel launch failed */
+  TSA_ENOTSUP = -4, /* dtype, layout or device not supported */
+  TSA_EBUSY = -5    /* serving: no free slot or scratch for the request */
+} tsa_status;
+
+typedef enum { TSA_F32 = 0, TSA_I16 = 1 } tsa_dtype;
+
+typedef struct {
+  const void* data; /* device pointer to nx*ny*nz elements */
+  int32_t dtype;    /* tsa_dtype */
+  int32_t reserved; /* must be 0 */
+  int64_t nx, ny, nz;
+} tsa_cube;
+
+typedef struct {
+  int64_t x0, y0, z0, x1, y1, z1; /* half-open box */
+} tsa_region;
+
+/* tsa_result.flags bits */
+#define TSA_FLAG_HIST_SKIPPED 1 /* histogram over [min,max] skipped: no valid voxel or non-finite min/max */
+#define TSA_FLAG_BAD_REGION 2   /* region_batch: this query's box was invalid (results left NaN / 0) */
+#define TSA_FLAG_PHASE3 4       /* region_batch: the median needed a third selection pass */
+
+typedef struct {
+  uint64_t count;     /* non-NaN voxels */
+  uint64_t nan_count; /* NaN voxels */
+  double mean;        /* (1/count) * sum x                      (Section 4.2) */
+  double m2;          /* sum (x - mean)^2                        (Section 4.2) */
+  double std;         /* sqrt(m2 / count): population form       (Section 4.2) */
+  double min, max;    /* totalOrder extremes, exact              (Section 4.1) */
+  double median;      /* lower median: rank floor((count-1)/2)   (Section 4.3) */
+  int32_t status;     /* TSA_OK, or an error found on the device */
+  int32_t flags;      /* TSA_FLAG_* */
+} tsa_result;         /* 72 bytes; NaN fields when count == 0 */
+
+/* Which operation a workspace is sized for. */
+typedef enum {
+  TSA_OP_MOMENTS = 0,
+  TSA_OP_HISTOGRAM = 1,
+  TSA_OP_MEDIAN = 2,
+  TSA_OP_STATS = 3,
+  TSA_OP_REGION_BATCH = 4
+} tsa_op;
+
+/* Tunables of tsa_region_batch (NULL = the library's tuned choice). */
+typedef struct {
+  int32_t tile_voxels;     /* target voxels per work item (power of two, >= 1024) */
+  int32_t block_threads;   /* 256 or 512 */
+  int32_t blocks_per_cu;   /* persistent blocks per compute unit, >= 1 */
+  int32_t cand_max;        /* largest bucket compacted for the median's last digits */
+} tsa_tune;
+
+/*
+ * Bytes of device workspace needed by one call of `op` on `cube` (region may
+ * be NULL = whole cube; nbins is used by TSA_OP_HISTOGRAM / TSA_OP_STATS /
+ * TSA_OP_REGION_BATCH; nq by TSA_OP_REGION_BATCH).  Returns 0 on bad
+ * arguments.  Never touches the device other than to query its properties.
+ */
+size_t tsa_workspace_bytes(int32_t op, const tsa_cube* cube, const tsa_region* region, int32_t nbins,
+                           int32_t nq);
+
+/*
+ * Global moments (Section 4.2, with min/max of Section 4.1): count, nan_count,
+ * mean, m2, std, min, max of the non-NaN voxels of `region` (host pointer or
+ * NULL).  Writes those fields and status/flags of *d_out (device pointer); the
+ * median field is left untouched.  Per-lane sums are float-float, block
+ * partials are merged in double in a fixed order (deterministic).
+ */
+int tsa_moments(const tsa_cube* cube, const tsa_region* region, tsa_result* d_out, void* d_ws,
+                size_t ws_bytes, tsa_stream_t stream);
+
+/*
+ * Fixed-range histogram (Section 4.1).  For a non-NaN value v (int16 is
+ * converted to float exactly): v < lo counts in d_outliers[0], v > hi in
+ * d_outliers[1]; otherwise bin b = min((int)((v - lo) * scale), nbins - 1)
+ * with scale = (float)nbins / (hi - lo), all in IEEE single precision
+ * (round-to-nearest, no fused multiply-add, denormals kept); lo == hi puts
+ * every v == lo in bin 0.  d_counts (uint64[nbins], device) and d_outliers
+ * (uint64[2], device, may be NULL) are overwritten.
+ * Errors (TSA_EINVAL): nbins outside [1, 65536]; lo or hi not finite;
+ * lo > hi; hi - lo or scale not finite, or scale == 0.
+ */
+int tsa_histogram(const tsa_cube* cube, const tsa_region* region, float lo, float hi, int32_t nbins,
+                  uint64_t* d_counts, uint64_t* d_outliers, void* d_ws, size_t ws_bytes,
+                  tsa_stream_t stream);
+
+/*
+ * Exact median (Section 4.3), read as the lower median: the non-NaN value of
+ * 0-based rank floor((count-1)/2) under totalOrder.  Found by radix selection
+ * on order-preserving 32-bit keys (12+12+8 key bits; no host round trip).
+ * Writes median, count, nan_count, status of *d_out; other fields untouched.
+ */
+int tsa_median(const tsa_cube* cube, const tsa_region* region, tsa_result* d_out, void* d_ws,
+               size_t ws_bytes, tsa_stream_t stream);
+
+/*
+ * The three statistics together: moments, the nbins histogram over the
+ * region's own [min, max], and the lower median, in two passes over the data
+ * (moments + first key digit; histogram + second key digit), then a pass over
+ * the few candidates left.  Fills every field of *d_out; d_counts
+ * (uint64[nbins]) and d_outliers (uint64[2], may be NULL) as in
+ * tsa_histogram.  When there is no valid voxel or min/max is not finite the
+ * histogram is all zero and TSA_FLAG_HIST_SKIPPED is set.
+ */
+int tsa_stats(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa_result* d_out,
+              uint64_t* d_counts, uint64_t* d_outliers, void* d_ws, size_t ws_bytes,
+              tsa_stream_t stream);
+
+/*
+ * Batched region queries ("local" statistics over user-defined regions,
+ * Section 4; the statistical mini-map of Section 4.5 is a regular grid of
+ * them).  For each of the nq boxes in d_regions (device array), computes what
+ * tsa_stats computes, with the histogram over the box's own [min, max]:
+ * d_results[q] (device, nq entries) and d_hists[q*nbins .. +nbins) (device,
+ * uint64).  All queries run in one persistent kernel fed by a device work
+ * queue of (query, phase, tile) items; no host round trip.  An invalid box
+ * sets TSA_FLAG_BAD_REGION and status TSA_EINVAL in its own result only.
+ * nq in [1, 1<<20], nbins in [1, 4096].  tune may be NULL.
+ */
+int tsa_region_batch(const tsa_cube* cube, const tsa_region* d_regions, int32_t nq, int32_t nbins,
+                     tsa_result* d_results, uint64_t* d_hists, const tsa_tune* tune, void* d_ws,
+                     size_t ws_bytes, tsa_stream_t stream);
+
+/* Human-readable text for a tsa_status value (static storage). */
+const char* tsa_status_string(int32_t status);
+
+/* Library version string (static storage). */
+const char* tsa_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSA_H */

@@ -203,15 +203,24 @@ def median(a: np.ndarray, region=None):
 
 def stats(a: np.ndarray, nbins: int, region=None) -> dict:
     """The full trio on one cube or region: moments, histogram over the
-    region's own [min, max], and the lower median."""
+    region's own [min, max] (skipped, all zero, when there is no valid value
+    or the range is not representable), and the lower median."""
     mo = moments(a, region)
     out = dict(mo)
     if mo["count"] == 0:
         out["counts"] = np.zeros(nbins, dtype=np.uint64)
         out["outliers"] = np.zeros(2, dtype=np.uint64)
         out["median"] = float("nan")
+        out["hist_skipped"] = True
         return out
     lo, hi = np.float32(mo["min"]), np.float32(mo["max"])
-    out["counts"], out["outliers"] = histogram(a, float(lo), float(hi), nbins, region)
+    try:
+        hist_scale(float(lo), float(hi), nbins)
+        out["counts"], out["outliers"] = histogram(a, float(lo), float(hi), nbins, region)
+        out["hist_skipped"] = False
+    except ValueError:  # infinite extremes or a range wider than single precision
+        out["counts"] = np.zeros(nbins, dtype=np.uint64)
+        out["outliers"] = np.zeros(2, dtype=np.uint64)
+        out["hist_skipped"] = True
     out["median"], _ = median(a, region)
     return out

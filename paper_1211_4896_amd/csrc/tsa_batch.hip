@@ -1,0 +1,870 @@
+// Batched region queries: thousands of sub-cube boxes, each getting moments,
+// a histogram over its own [min, max] and its lower median, in ONE
+// persistent kernel.
+//
+// Work items are tickets drawn from one device counter.  With T1 tiles in the
+// whole batch (each box cut into row tiles), ticket t means
+//   t in [0, T1)      phase 1: moments + first key digit of tile t
+//   t in [T1, 2 T1)   phase 2: histogram + second key digit (+ candidate copy,
+//                     + second moment about the mean) of tile t - T1
+//   t in [2 T1, 3 T1) phase 3 (rare): last key digit of tile t - 2 T1
+// The block that finishes the last tile of a box's phase runs that box's
+// epilogue (merge, digit selection, next-phase set-up).  A phase-2 tile waits
+// for its box's phase-1 epilogue; phase-3 tickets wait until every box has
+// finished phase 2.  Tickets are handed out in increasing order, so every
+// wait is on tiles already taken by running blocks that never wait on
+// anything later: the kernel needs no co-resident grid and cannot deadlock.
+// Every wait is bounded; a block that gives up raises an error word and the
+// boxes left unfinished report TSA_EDEVICE.
+#include <math.h>
+
+#include "tsa_internal.hpp"
+
+namespace tsa {
+
+constexpr uint32_t kDefTileUnits = 16384;  // 16-byte vectors per tile (64K float32 voxels)
+constexpr uint32_t kDefCandMax = 65536;    // largest first-digit bucket copied out
+constexpr uint32_t kPoolKeys = 1u << 23;   // candidate pool (keys) shared by the batch
+constexpr int kBBlock = 256;
+constexpr int kMaxQueries = 65536;
+constexpr uint32_t kSpinLimit = 1u << 24;        // polls per wait, at most
+constexpr uint64_t kWaitTicks = 100000000ull * 10;  // 10 s of the 100 MHz wall clock
+
+struct QGeom {
+  int64_t v_origin;
+  uint64_t volume;
+  uint32_t ly, nrows, vpr, rpt, ntiles, head_skip, last_valid, valid;
+  Magic ly_m, vpr_m;
+};
+
+struct QState {
+  uint32_t done1, done2, done3;
+  uint32_t p1_ready;
+  uint32_t skip2, need3, compact, cand_base, cand_n, cand_fill;
+  uint32_t prefix, hist_ok, var_on, finished;
+  float lo, hi, scale, shift;
+  int32_t vscale, pad;
+  uint64_t n, k;
+};
+
+struct BatchHdr {
+  uint64_t T1;
+  uint64_t ticket;
+  uint32_t p2_done, any3, pool_top, err;
+  uint32_t nq, pad;
+};
+
+struct BArgs {
+  const void* base;
+  int64_t nx, ny, nz;
+  const tsa_region* regions;
+  int32_t nq, nbins;
+  uint32_t rshift, tile_units, max_tiles, cand_max, pool_keys;
+  int32_t vec;
+  tsa_result* results;
+  uint64_t* hists;
+  BatchHdr* hdr;
+  QGeom* geom;
+  QState* st;
+  uint64_t* tile_base;
+  Partial* parts1;
+  float2* parts2;
+  uint32_t* digits;
+  uint32_t* pool;
+};
+
+// ---------------------------------------------------------------------------
+// planning
+// ---------------------------------------------------------------------------
+TSA_DEV Magic dev_magic(uint32_t d) {
+  uint32_t l = 0;
+  while ((1ull << l) < (uint64_t)d) ++l;
+  Magic g;
+  g.m = (uint32_t)((((1ull << 32) * ((1ull << l) - (uint64_t)d)) / (uint64_t)d) + 1ull);
+  g.s1 = l ? 1u : 0u;
+  g.s2 = l ? l - 1u : 0u;
+  return g;
+}
+
+template <int DT>
+__global__ void k_bplan(BArgs a) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= a.nq) return;
+  const tsa_region r = a.regions[q];
+  QGeom g;
+  memset(&g, 0, sizeof(g));
+  bool ok = r.x0 >= 0 && r.y0 >= 0 && r.z0 >= 0 && r.x1 <= a.nx && r.y1 <= a.ny && r.z1 <= a.nz && r.x0 < r.x1 &&
+            r.y0 < r.y1 && r.z0 < r.z1;
+  tsa_result res;
+  res.count = 0;
+  res.nan_count = 0;
+  res.mean = res.m2 = res.std = res.min = res.max = res.median = __builtin_nan("");
+  res.status = TSA_OK;
+  res.flags = 0;
+  if (ok) {
+    const int64_t lx = r.x1 - r.x0, ly = r.y1 - r.y0, lz = r.z1 - r.z0;
+    const uint64_t vol = (uint64_t)lx * (uint64_t)ly * (uint64_t)lz;
+    const uint64_t nrows = (uint64_t)ly * (uint64_t)lz;
+    ok = vol < (1ull << 32) && nrows < (1ull << 32);
+    if (ok) {
+      const int64_t epv = a.vec ? (DT == 0 ? 4 : 8) : 1;
+      g.volume = vol;
+      g.ly = (uint32_t)ly;
+      g.nrows = (uint32_t)nrows;
+      if (a.vec) {
+        const int64_t c0 = r.x0 / epv, c1 = (r.x1 + epv - 1) / epv;
+        g.v_origin = c0 + (a.nx / epv) * (r.y0 + a.ny * r.z0);
+        g.vpr = (uint32_t)(c1 - c0);
+        g.head_skip = (uint32_t)(r.x0 % epv);
+        g.last_valid = (uint32_t)(r.x1 - (c1 - 1) * epv);
+      } else {
+        g.v_origin = r.x0 + a.nx * (r.y0 + a.ny * r.z0);
+        g.vpr = (uint32_t)lx;
+        g.head_skip = 0;
+        g.last_valid = 1;
+      }
+      uint64_t rpt = a.tile_units / g.vpr;
+      if (rpt < 1) rpt = 1;
+      uint64_t nt = (g.nrows + rpt - 1) / rpt;
+      if (nt > a.max_tiles) {
+        rpt = (g.nrows + a.max_tiles - 1) / a.max_tiles;
+        nt = (g.nrows + rpt - 1) / rpt;
+      }
+      ok = rpt * g.vpr < (1ull << 31);
+      g.rpt = (uint32_t)rpt;
+      g.ntiles = ok ? (uint32_t)nt : 0u;
+      g.ly_m = dev_magic(g.ly);
+      g.vpr_m = dev_magic(g.vpr);
+      g.valid = ok ? 1u : 0u;
+      res.nan_count = vol;  // until the moments say otherwise
+    }
+  }
+  if (!ok) {
+    g.valid = 0;
+    g.ntiles = 0;
+    res.status = TSA_EINVAL;
+    res.flags = TSA_FLAG_BAD_REGION;
+    atomicAdd(&a.hdr->p2_done, 1u);  // nothing to wait for
+  }
+  a.geom[q] = g;
+  QState s;
+  memset(&s, 0, sizeof(s));
+  a.st[q] = s;
+  a.results[q] = res;
+}
+
+// Exclusive scan of the tile counts (one block) and the batch header.
+__global__ __launch_bounds__(1024) void k_bscan(BArgs a) {
+  __shared__ uint64_t wsum[16];
+  const int t = threadIdx.x, bs = blockDim.x;
+  const int per = (a.nq + bs - 1) / bs;
+  const int q0 = t * per;
+  uint64_t local = 0;
+  for (int i = 0; i < per; ++i)
+    if (q0 + i < a.nq) local += a.geom[q0 + i].ntiles;
+  const int lane = t % kWave, w = t / kWave;
+  uint64_t inc = local;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint64_t y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
+  }
+  if (lane == kWave - 1) wsum[w] = inc;
+  __syncthreads();
+  uint64_t base = inc - local, total = 0;
+  for (int i = 0; i < bs / kWave; ++i) {
+    if (i < w) base += wsum[i];
+    total += wsum[i];
+  }
+  for (int i = 0; i < per; ++i) {
+    if (q0 + i < a.nq) {
+      a.tile_base[q0 + i] = base;
+      base += a.geom[q0 + i].ntiles;
+    }
+  }
+  if (t == 0) {
+    a.tile_base[a.nq] = total;
+    a.hdr->T1 = total;
+    a.hdr->nq = (uint32_t)a.nq;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// block helpers of the persistent kernel
+// ---------------------------------------------------------------------------
+struct BShared {
+  uint64_t t;
+  uint32_t q, tile, last, flag;
+  uint64_t u64a, u64b;
+  MomShared mom;
+  double mn[kBBlock], mm[kBBlock], mq[kBBlock];
+  uint32_t kmin[kBBlock], kmax[kBBlock];
+  uint64_t wsum[16];
+  uint32_t found;
+  uint32_t sel_digit;
+  uint64_t sel_cum, sel_bucket;
+};
+
+// Thread 0 waits until *p >= v (bounded); result broadcast to the block.
+TSA_DEV bool block_wait_ge(const uint32_t* p, uint32_t v, uint32_t* err, BShared& sh) {
+  if (threadIdx.x == 0) {
+    uint32_t ok = 0;
+    const uint64_t t0 = wall_clock64();
+    for (uint32_t it = 0; it < kSpinLimit; ++it) {
+      if (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= v) {
+        ok = 1;
+        break;
+      }
+      if ((it & 255u) == 255u) {
+        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        if (wall_clock64() - t0 > kWaitTicks) break;
+      }
+      __builtin_amdgcn_s_sleep(4);
+    }
+    if (!ok) atomicOr(err, 1u);
+    sh.flag = ok;
+  }
+  __syncthreads();
+  const bool ok = sh.flag != 0;
+  __syncthreads();
+  return ok;
+}
+
+// Block-wide choice of the digit holding rank k in a histogram of nb bins
+// (u32 counts).  Returns false when k is not inside the histogram.
+TSA_DEV bool block_select_u32(const uint32_t* hist, int nb, uint64_t k, BShared& sh, uint32_t* digit,
+                              uint64_t* cum_before, uint64_t* bucket) {
+  const int t = threadIdx.x, bs = blockDim.x;
+  const int per = (nb + bs - 1) / bs;
+  const int b0 = t * per;
+  uint64_t local = 0;
+  for (int i = 0; i < per; ++i)
+    if (b0 + i < nb) local += hist[b0 + i];
+  const int lane = t % kWave, w = t / kWave;
+  uint64_t inc = local;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint64_t y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
+  }
+  if (lane == kWave - 1) sh.wsum[w] = inc;
+  if (t == 0) sh.found = 0;
+  __syncthreads();
+  uint64_t base = inc - local;
+  for (int i = 0; i < w; ++i) base += sh.wsum[i];
+  if (local > 0 && k >= base && k < base + local) {
+    uint64_t cum = base;
+    int d = b0;
+    for (int i = 0; i < per; ++i) {
+      const uint64_t h = (b0 + i < nb) ? hist[b0 + i] : 0;
+      if (k < cum + h) {
+        d = b0 + i;
+        break;
+      }
+      cum += h;
+    }
+    sh.sel_digit = (uint32_t)d;
+    sh.sel_cum = cum;
+    sh.sel_bucket = hist[d];
+    sh.found = 1;
+  }
+  __syncthreads();
+  const bool found = sh.found != 0;
+  *digit = sh.sel_digit;
+  *cum_before = sh.sel_cum;
+  *bucket = sh.sel_bucket;
+  __syncthreads();
+  return found;
+}
+
+TSA_DEV double bvalue_of_key(uint32_t k, int dtype) {
+  return dtype == 0 ? (double)__uint_as_float(f32bits_of_key(k)) : (double)i16_of_key(k);
+}
+
+TSA_DEV void chan_merge_b(double& na, double& ma, double& qa, double nb, double mb, double qb) {
+  if (nb == 0.0) return;
+  if (na == 0.0) {
+    na = nb;
+    ma = mb;
+    qa = qb;
+    return;
+  }
+  const double n = na + nb;
+  const double d = mb - ma;
+  ma = ma + d * (nb / n);
+  qa = qa + qb + d * d * (na * nb / n);
+  na = n;
+}
+
+TSA_DEV void partial_stats_b(const Partial& p, int dtype, double& n, double& m, double& q) {
+  n = (double)p.n;
+  if (p.n == 0) {
+    m = q = 0.0;
+    return;
+  }
+  if (dtype == 0) {
+    const double S = (double)p.sh + (double)p.sl;
+    const double Q = (double)p.qh + (double)p.ql;
+    m = S / n;
+    q = Q - S * m;
+  } else {
+    const __int128 num = (__int128)p.qi * (__int128)p.n - (__int128)p.si * (__int128)p.si;
+    const int64_t hi = (int64_t)(num >> 64);
+    const uint64_t lo = (uint64_t)num;
+    m = (double)p.si / n;
+    q = ((double)hi * 18446744073709551616.0 + (double)lo) / n;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// epilogues (whole block)
+// ---------------------------------------------------------------------------
+template <int DT>
+TSA_DEV void epilogue1(const BArgs& a, uint32_t q, BShared& sh) {
+  const QGeom& g = a.geom[q];
+  QState& s = a.st[q];
+  tsa_result& R = a.results[q];
+  const int t = threadIdx.x, bs = blockDim.x;
+  const uint64_t tb = a.tile_base[q];
+  // fixed-order Chan merge of the tile partials
+  double n = 0.0, m = 0.0, m2 = 0.0;
+  uint32_t mn = 0xFFFFFFFFu, mx = 0u;
+  for (uint32_t i = t; i < g.ntiles; i += bs) {
+    const Partial p = a.parts1[tb + i];
+    double pn, pm, pq;
+    partial_stats_b(p, DT, pn, pm, pq);
+    chan_merge_b(n, m, m2, pn, pm, pq);
+    if (p.n) {
+      mn = min(mn, p.kmin);
+      mx = max(mx, p.kmax);
+    }
+  }
+  sh.mn[t] = n;
+  sh.mm[t] = m;
+  sh.mq[t] = m2;
+  sh.kmin[t] = mn;
+  sh.kmax[t] = mx;
+  __syncthreads();
+  for (int s2 = bs / 2; s2 > 0; s2 >>= 1) {
+    if (t < s2) {
+      double x = sh.mn[t], y = sh.mm[t], z = sh.mq[t];
+      chan_merge_b(x, y, z, sh.mn[t + s2], sh.mm[t + s2], sh.mq[t + s2]);
+      sh.mn[t] = x;
+      sh.mm[t] = y;
+      sh.mq[t] = z;
+      sh.kmin[t] = min(sh.kmin[t], sh.kmin[t + s2]);
+      sh.kmax[t] = max(sh.kmax[t], sh.kmax[t + s2]);
+    }
+    __syncthreads();
+  }
+  const uint64_t cnt = (uint64_t)sh.mn[0];
+  const double mean = sh.mm[0];
+  const uint32_t kmin = sh.kmin[0], kmax = sh.kmax[0];
+  const uint32_t* dig = a.digits + (size_t)q * kBins1;
+  bool skip2 = false;
+  if (t == 0) {
+    R.count = cnt;
+    R.nan_count = g.volume - cnt;
+    s.n = cnt;
+    if (cnt == 0) {
+      R.flags |= TSA_FLAG_HIST_SKIPPED;
+      s.finished = 1;
+    } else {
+      const double vmin = bvalue_of_key(kmin, DT), vmax = bvalue_of_key(kmax, DT);
+      R.min = vmin;
+      R.max = vmax;
+      if (kmin == kmax) {
+        R.mean = vmin;
+        R.m2 = 0.0;
+        R.std = 0.0;
+        R.median = vmin;
+        a.hists[(size_t)q * a.nbins] = cnt;  // lo == hi: every value in bin 0
+        s.finished = 1;
+      } else {
+        const double q2 = sh.mq[0] > 0.0 ? sh.mq[0] : 0.0;
+        R.mean = mean;
+        R.m2 = q2;
+        R.std = sqrt(q2 / (double)cnt);
+      }
+    }
+  }
+  skip2 = cnt == 0 || kmin == kmax;
+  if (!skip2) {
+    const uint64_t k = (cnt - 1) / 2;
+    uint32_t d;
+    uint64_t cum, bucket;
+    const bool found = block_select_u32(dig, kBins1, k, sh, &d, &cum, &bucket);
+    // the first-digit counts become the second-digit counts: clear them
+    for (int i = t; i < kBins1; i += bs) a.digits[(size_t)q * kBins1 + i] = 0u;
+    if (t == 0) {
+      if (!found) {
+        R.status = TSA_EDEVICE;
+        skip2 = true;
+        s.finished = 1;
+      } else {
+        s.prefix = d << kShift1;
+        s.k = k - cum;
+        float lo = (float)bvalue_of_key(kmin, DT), hi = (float)bvalue_of_key(kmax, DT), scale = 0.f;
+        uint32_t ok = 0;
+        if (isfinite(lo) && isfinite(hi)) {
+          const float width = hi - lo;
+          if (isfinite(width)) {
+            scale = (float)a.nbins / width;
+            ok = (isfinite(scale) && scale != 0.0f) ? 1u : 0u;
+          }
+        }
+        s.lo = lo;
+        s.hi = hi;
+        s.scale = scale;
+        s.hist_ok = ok;
+        if (!ok) R.flags |= TSA_FLAG_HIST_SKIPPED;
+        s.var_on = (DT == 0 && isfinite(mean)) ? 1u : 0u;
+        s.shift = s.var_on ? (float)mean : 0.0f;
+        s.vscale = s.var_on ? var_scale_exp(fmax(fabs((double)hi - (double)s.shift), fabs((double)lo - (double)s.shift)))
+                            : 0;
+        s.compact = 0;
+        if (bucket <= a.cand_max) {
+          const uint32_t base = atomicAdd(&a.hdr->pool_top, (uint32_t)bucket);
+          if ((uint64_t)base + bucket <= a.pool_keys) {
+            s.compact = 1;
+            s.cand_base = base;
+            s.cand_n = (uint32_t)bucket;
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();  // every thread's clearing of the digit counts precedes the release below
+  if (t == 0) {
+    s.skip2 = skip2 ? 1u : 0u;
+    __threadfence();
+    __hip_atomic_store(&s.p1_ready, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+}
+
+template <int DT>
+TSA_DEV void epilogue2(const BArgs& a, uint32_t q, BShared& sh, uint32_t* lds) {
+  const QGeom& g = a.geom[q];
+  QState& s = a.st[q];
+  tsa_result& R = a.results[q];
+  const int t = threadIdx.x, bs = blockDim.x;
+  if (!s.skip2) {
+    const uint64_t n = s.n;
+    if (DT == 0 && s.var_on) {
+      const uint64_t tb = a.tile_base[q];
+      double x = 0.0;
+      for (uint32_t i = t; i < g.ntiles; i += bs) x += (double)a.parts2[tb + i].x + (double)a.parts2[tb + i].y;
+      sh.mm[t] = x;
+      __syncthreads();
+      for (int s2 = bs / 2; s2 > 0; s2 >>= 1) {
+        if (t < s2) sh.mm[t] += sh.mm[t + s2];
+        __syncthreads();
+      }
+      if (t == 0) {
+        const double dm = R.mean - (double)s.shift;
+        double m2 = ldexp(sh.mm[0], -2 * s.vscale) - (double)n * dm * dm;
+        if (!(m2 > 0.0)) m2 = 0.0;
+        R.m2 = m2;
+        R.std = sqrt(m2 / (double)n);
+      }
+      __syncthreads();
+    }
+    uint32_t* dig = a.digits + (size_t)q * kBins1;
+    uint32_t d;
+    uint64_t cum, bucket;
+    bool found = block_select_u32(dig, kBins2, s.k, sh, &d, &cum, &bucket);
+    const uint32_t prefix = s.prefix | (d << kShift2);
+    const uint64_t k2 = s.k - cum;
+    if (!found) {
+      if (t == 0) {
+        R.status = TSA_EDEVICE;
+        s.finished = 1;
+      }
+    } else if (DT == 1) {  // int16 keys have no bits below the second digit
+      if (t == 0) {
+        R.median = bvalue_of_key(prefix, DT);
+        s.finished = 1;
+      }
+    } else if (s.compact) {
+      // last 8 bits from the copied candidates
+      for (int i = t; i < kBins3; i += bs) lds[i] = 0u;
+      __syncthreads();
+      const uint32_t* c = a.pool + s.cand_base;
+      const uint32_t nc = min(s.cand_n, __hip_atomic_load(&s.cand_fill, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      const uint32_t p2 = prefix >> kShift2;
+      for (uint32_t i = t; i < nc; i += bs) {
+        const uint32_t key = c[i];
+        if ((key >> kShift2) == p2) lds_inc(lds, key & 0xFFu);
+      }
+      __syncthreads();
+      uint32_t d3;
+      uint64_t cum3, b3;
+      found = block_select_u32(lds, kBins3, k2, sh, &d3, &cum3, &b3);
+      if (t == 0) {
+        if (found)
+          R.median = bvalue_of_key(prefix | d3, DT);
+        else
+          R.status = TSA_EDEVICE;
+        s.finished = 1;
+      }
+    } else {
+      for (int i = t; i < kBins3; i += bs) dig[i] = 0u;
+      if (t == 0) {
+        s.prefix = prefix;
+        s.k = k2;
+        s.need3 = 1;
+        R.flags |= TSA_FLAG_PHASE3;
+        __hip_atomic_store(&a.hdr->any3, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  }
+  __syncthreads();
+  if (t == 0) {
+    __threadfence();
+    atomicAdd(&a.hdr->p2_done, 1u);
+  }
+  __syncthreads();
+}
+
+template <int DT>
+TSA_DEV void epilogue3(const BArgs& a, uint32_t q, BShared& sh) {
+  QState& s = a.st[q];
+  uint32_t d;
+  uint64_t cum, bucket;
+  const bool found = block_select_u32(a.digits + (size_t)q * kBins1, kBins3, s.k, sh, &d, &cum, &bucket);
+  if (threadIdx.x == 0) {
+    if (found)
+      a.results[q].median = bvalue_of_key(s.prefix | d, DT);
+    else
+      a.results[q].status = TSA_EDEVICE;
+    s.finished = 1;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// per-tile accumulators
+// ---------------------------------------------------------------------------
+template <int DT>
+struct BPass1 {
+  MomAcc<DT> mom;
+  Digit1Acc<DT> d1;
+  template <class T>
+  TSA_DEV void operator()(T raw, bool in) {
+    mom(raw, in);
+    d1(raw, in);
+  }
+  TSA_DEV void chunk() {}
+};
+
+template <int DT>
+struct BPass2 {
+  HistAcc h;
+  Level2Acc<DT> l2;
+  VarAcc var;
+  bool hist_on, var_on;
+  template <class T>
+  TSA_DEV void operator()(T raw, bool in) {
+    if (hist_on) h(raw, in);
+    l2(raw, in);
+    if constexpr (DT == 0) {
+      if (var_on) var(raw, in);
+    }
+  }
+  TSA_DEV void chunk() {}
+};
+
+template <int DT, bool VEC, bool NT, class F>
+TSA_DEV void walk_tile(const BArgs& a, const QGeom& g, uint32_t tile, F& f) {
+  const uint32_t r0 = tile * g.rpt;
+  const uint32_t nr = min(g.rpt, g.nrows - r0);
+  const int64_t epv = VEC ? (DT == 0 ? 4 : 8) : 1;
+  const int64_t ys = a.nx / epv, zs = (a.nx / epv) * a.ny;
+  walk_rows<DT, VEC, kUnroll, NT>(a.base, g.v_origin, ys, zs, g.ly, g.ly_m, g.vpr, g.vpr_m, g.head_skip,
+                                  g.last_valid, r0, nr, f);
+}
+
+// ---------------------------------------------------------------------------
+// the persistent kernel
+// ---------------------------------------------------------------------------
+template <int DT, bool VEC, bool NT>
+__global__ __launch_bounds__(kBBlock) void k_batch(BArgs a) {
+  extern __shared__ uint32_t lds[];
+  __shared__ BShared sh;
+  const int t = threadIdx.x;
+  const uint64_t T1 = a.hdr->T1;
+  for (;;) {
+    if (t == 0) sh.t = atomicAdd((unsigned long long*)&a.hdr->ticket, 1ull);
+    __syncthreads();
+    const uint64_t tk = sh.t;
+    __syncthreads();
+    int phase;
+    uint64_t lt;
+    if (tk < T1) {
+      phase = 1;
+      lt = tk;
+    } else if (tk < 2 * T1) {
+      phase = 2;
+      lt = tk - T1;
+    } else {
+      phase = 3;
+      lt = tk - 2 * T1;
+      if (!block_wait_ge(&a.hdr->p2_done, (uint32_t)a.nq, &a.hdr->err, sh)) return;
+      if (__hip_atomic_load(&a.hdr->any3, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0 || lt >= T1) return;
+    }
+    // ticket -> (query, tile): binary search over the tile prefix sums
+    if (t == 0) {
+      uint32_t lo = 0, hi = (uint32_t)a.nq;  // tile_base[lo] <= lt < tile_base[hi]
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a.tile_base[mid] <= lt)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      sh.q = lo;
+      sh.tile = (uint32_t)(lt - a.tile_base[lo]);
+    }
+    __syncthreads();
+    const uint32_t q = sh.q, tile = sh.tile;
+    __syncthreads();
+    const QGeom& g = a.geom[q];
+    QState& s = a.st[q];
+
+    if (phase == 1) {
+      lds_zero(lds, kBins1);
+      __syncthreads();
+      BPass1<DT> f{MomAcc<DT>{}, Digit1Acc<DT>{lds, 0u, 0u}};
+      walk_tile<DT, VEC, NT>(a, g, tile, f);
+      block_store_partial(f.mom, sh.mom, a.parts1 + a.tile_base[q] + tile);
+      __syncthreads();
+      uint32_t* dig = a.digits + (size_t)q * kBins1;
+      for (int b = t; b < kBins1; b += kBBlock) {
+        const uint32_t c = lds[b];
+        if (c) atomicAdd(dig + b, c);
+      }
+    } else if (phase == 2) {
+      if (!block_wait_ge(&s.p1_ready, 1u, &a.hdr->err, sh)) return;
+      if (!s.skip2) {
+        const uint32_t hsize = (uint32_t)a.nbins << a.rshift;
+        uint32_t* l2 = lds + hsize;
+        lds_zero(lds, hsize + kBins2);
+        __syncthreads();
+        const bool hist_on = s.hist_ok != 0, var_on = DT == 0 && s.var_on != 0;
+        BPass2<DT> f{HistAcc{lds, s.lo, s.hi, s.scale, a.nbins - 1, a.rshift, (uint32_t)t & ((1u << a.rshift) - 1u)},
+                     Level2Acc<DT>{l2, s.prefix >> kShift1, s.compact != 0, a.pool + s.cand_base, &s.cand_fill,
+                                   s.cand_n},
+                     VarAcc{s.shift, s.vscale}, hist_on, var_on};
+        walk_tile<DT, VEC, NT>(a, g, tile, f);
+        __syncthreads();
+        if (hist_on) lds_flush(lds, (uint32_t)a.nbins, a.rshift, a.hists + (size_t)q * a.nbins);
+        uint32_t* dig = a.digits + (size_t)q * kBins1;
+        for (int b = t; b < kBins2; b += kBBlock) {
+          const uint32_t c = l2[b];
+          if (c) atomicAdd(dig + b, c);
+        }
+        if (var_on) {
+          __syncthreads();
+          float h, l;
+          two_sum(f.var.qh, f.var.ql, h, l);
+          f.var.qh = h;
+          f.var.ql = l;
+#pragma unroll
+          for (int o = 32; o > 0; o >>= 1) {
+            const float bqh = __shfl_xor(f.var.qh, o), bql = __shfl_xor(f.var.ql, o);
+            dw_add(f.var.qh, f.var.ql, bqh, bql);
+          }
+          const int w = t / kWave, lane = t % kWave;
+          if (lane == 0) {
+            sh.mom.qh[w] = f.var.qh;
+            sh.mom.ql[w] = f.var.ql;
+          }
+          __syncthreads();
+          if (t == 0) {
+            float qh = sh.mom.qh[0], ql = sh.mom.ql[0];
+            for (int i = 1; i < kBBlock / kWave; ++i) dw_add(qh, ql, sh.mom.qh[i], sh.mom.ql[i]);
+            a.parts2[a.tile_base[q] + tile] = make_float2(qh, ql);
+          }
+        }
+      }
+    } else {
+      if (t == 0) sh.flag = s.need3;
+      __syncthreads();
+      const bool need3 = sh.flag != 0;
+      __syncthreads();
+      if (!need3) continue;
+      lds_zero(lds, kBins3);
+      __syncthreads();
+      Level3Acc<DT> f{lds, s.prefix >> kShift2};
+      walk_tile<DT, VEC, NT>(a, g, tile, f);
+      __syncthreads();
+      uint32_t* dig = a.digits + (size_t)q * kBins1;
+      for (int b = t; b < kBins3; b += kBBlock) {
+        const uint32_t c = lds[b];
+        if (c) atomicAdd(dig + b, c);
+      }
+    }
+    // count the tile; the block finishing the last one runs the epilogue
+    __syncthreads();
+    if (t == 0) {
+      __threadfence();
+      uint32_t* cnt = phase == 1 ? &s.done1 : phase == 2 ? &s.done2 : &s.done3;
+      const uint32_t prev = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      sh.last = prev + 1 == g.ntiles ? 1u : 0u;
+      __threadfence();
+    }
+    __syncthreads();
+    if (sh.last) {
+      if (phase == 1)
+        epilogue1<DT>(a, q, sh);
+      else if (phase == 2)
+        epilogue2<DT>(a, q, sh, lds);
+      else
+        epilogue3<DT>(a, q, sh);
+    }
+    __syncthreads();
+  }
+}
+
+// Boxes left unfinished (a bounded wait gave up) report a device error.
+__global__ void k_bfinal(BArgs a) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= a.nq) return;
+  if (a.geom[q].valid && !a.st[q].finished) a.results[q].status = TSA_EDEVICE;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+struct BLayout {
+  size_t hdr, geom, st, tile_base, parts1, parts2, digits, pool, total;
+  uint32_t max_tiles;
+};
+
+static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static BLayout batch_layout(int32_t nq) {
+  BLayout L;
+  uint32_t mt = (1u << 20) / (uint32_t)nq;
+  if (mt > 256) mt = 256;
+  if (mt < 16) mt = 16;
+  L.max_tiles = mt;
+  size_t o = 0;
+  L.hdr = o;
+  o = al(o + sizeof(BatchHdr));
+  L.geom = o;
+  o = al(o + sizeof(QGeom) * (size_t)nq);
+  L.st = o;
+  o = al(o + sizeof(QState) * (size_t)nq);
+  L.tile_base = o;
+  o = al(o + 8 * ((size_t)nq + 1));
+  L.parts1 = o;
+  o = al(o + sizeof(Partial) * (size_t)nq * mt);
+  L.parts2 = o;
+  o = al(o + sizeof(float2) * (size_t)nq * mt);
+  L.digits = o;
+  o = al(o + 4 * (size_t)kBins1 * nq);
+  L.pool = o;
+  o = al(o + 4 * (size_t)kPoolKeys);
+  L.total = o;
+  return L;
+}
+
+size_t batch_ws_bytes(const tsa_cube* cube, int32_t nbins, int32_t nq) {
+  if (check_cube(cube) != TSA_OK || nq < 1 || nq > kMaxQueries || nbins < 1 || nbins > 4096) return 0;
+  return batch_layout(nq).total;
+}
+
+static void bfill(void* p, size_t words, hipStream_t s);
+
+int run_region_batch(const tsa_cube* cube, const tsa_region* d_regions, int32_t nq, int32_t nbins,
+                     tsa_result* d_results, uint64_t* d_hists, const tsa_tune* tune, void* d_ws, size_t ws_bytes,
+                     tsa_stream_t stream) {
+  int st = check_cube(cube);
+  if (st) return st;
+  if (!d_regions || !d_results || !d_hists || nq < 1 || nq > kMaxQueries || nbins < 1 || nbins > 4096)
+    return TSA_EINVAL;
+  const BLayout L = batch_layout(nq);
+  if (!d_ws || ws_bytes < L.total) return TSA_ENOMEM;
+  DevInfo dev;
+  if ((st = device_info(&dev))) return st;
+  uint32_t tile_units = kDefTileUnits, cand_max = kDefCandMax;
+  int bpc = 4;
+  if (tune) {
+    if (tune->tile_voxels >= 1024) tile_units = (uint32_t)tune->tile_voxels / (cube->dtype == TSA_F32 ? 4 : 8);
+    if (tune->blocks_per_cu >= 1 && tune->blocks_per_cu <= 16) bpc = tune->blocks_per_cu;
+    if (tune->cand_max >= 0) cand_max = (uint32_t)tune->cand_max;
+    if (tune->block_threads != 0 && tune->block_threads != kBBlock) return TSA_ENOTSUP;
+  }
+  if (tile_units < 256) tile_units = 256;
+  const int epv = cube->dtype == TSA_F32 ? 4 : 8;
+  const bool vec = ((uintptr_t)cube->data % 16) == 0 && (cube->nx % epv) == 0;
+  if (!vec) tile_units *= (uint32_t)epv;  // scalar units are elements
+  char* ws = (char*)d_ws;
+  BArgs a;
+  a.base = cube->data;
+  a.nx = cube->nx;
+  a.ny = cube->ny;
+  a.nz = cube->nz;
+  a.regions = d_regions;
+  a.nq = nq;
+  a.nbins = nbins;
+  a.rshift = nbins <= 1024 ? 2u : nbins <= 2048 ? 1u : 0u;
+  a.tile_units = tile_units;
+  a.max_tiles = L.max_tiles;
+  a.cand_max = cand_max;
+  a.pool_keys = kPoolKeys;
+  a.vec = vec ? 1 : 0;
+  a.results = d_results;
+  a.hists = d_hists;
+  a.hdr = (BatchHdr*)(ws + L.hdr);
+  a.geom = (QGeom*)(ws + L.geom);
+  a.st = (QState*)(ws + L.st);
+  a.tile_base = (uint64_t*)(ws + L.tile_base);
+  a.parts1 = (Partial*)(ws + L.parts1);
+  a.parts2 = (float2*)(ws + L.parts2);
+  a.digits = (uint32_t*)(ws + L.digits);
+  a.pool = (uint32_t*)(ws + L.pool);
+  hipStream_t s = (hipStream_t)stream;
+  const size_t lds1 = (size_t)kBins1 * 4;
+  const size_t lds2 = (((size_t)nbins << a.rshift) + kBins2) * 4;
+  const size_t lds = lds1 > lds2 ? lds1 : lds2;
+  bfill(a.hdr, sizeof(BatchHdr) / 4, s);
+  bfill(a.digits, (size_t)kBins1 * nq, s);
+  bfill(d_hists, (size_t)nbins * nq * 2, s);
+  const int pb = (nq + 255) / 256;
+  if (cube->dtype == TSA_F32)
+    TSA_TRACED("batch_plan", s, hipLaunchKernelGGL(k_bplan<0>, dim3(pb), dim3(256), 0, s, a));
+  else
+    TSA_TRACED("batch_plan", s, hipLaunchKernelGGL(k_bplan<1>, dim3(pb), dim3(256), 0, s, a));
+  TSA_TRACED("batch_scan", s, hipLaunchKernelGGL(k_bscan, dim3(1), dim3(1024), 0, s, a));
+  const int grid = dev.cus * bpc;
+  if (cube->dtype == TSA_F32) {
+    if (vec)
+      TSA_TRACED("batch", s, hipLaunchKernelGGL((k_batch<0, true, true>), dim3(grid), dim3(kBBlock), lds, s, a));
+    else
+      TSA_TRACED("batch", s, hipLaunchKernelGGL((k_batch<0, false, false>), dim3(grid), dim3(kBBlock), lds, s, a));
+  } else {
+    if (vec)
+      TSA_TRACED("batch", s, hipLaunchKernelGGL((k_batch<1, true, true>), dim3(grid), dim3(kBBlock), lds, s, a));
+    else
+      TSA_TRACED("batch", s, hipLaunchKernelGGL((k_batch<1, false, false>), dim3(grid), dim3(kBBlock), lds, s, a));
+  }
+  TSA_TRACED("batch_final", s, hipLaunchKernelGGL(k_bfinal, dim3(pb), dim3(256), 0, s, a));
+  return hipGetLastError() == hipSuccess ? TSA_OK : TSA_EDEVICE;
+}
+
+__global__ void k_bfill32(uint32_t* __restrict__ p, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+static void bfill(void* p, size_t words, hipStream_t s) {
+  if (!words) return;
+  int blocks = (int)((words + 255) / 256);
+  if (blocks > 2048) blocks = 2048;
+  TSA_TRACED("fill", s, hipLaunchKernelGGL(k_bfill32, dim3(blocks), dim3(256), 0, s, (uint32_t*)p, (uint64_t)words));
+}
+
+}  // namespace tsa

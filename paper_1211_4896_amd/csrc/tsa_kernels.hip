@@ -1,0 +1,872 @@
+// Whole-cube and single-region kernels: moments, histogram, radix-select
+// median, and the fused two-pass trio.
+#include <math.h>
+
+#include "tsa_internal.hpp"
+
+namespace tsa {
+
+// ---------------------------------------------------------------------------
+// small utility kernels
+// ---------------------------------------------------------------------------
+__global__ void k_fill32(uint32_t* __restrict__ p, uint64_t n, uint32_t v) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// moments pass: one Partial per block
+// ---------------------------------------------------------------------------
+template <int DT, bool VEC, bool NT>
+__global__ __launch_bounds__(1024) void k_moments(Geom g, Partial* __restrict__ parts) {
+  __shared__ MomShared sm;
+  MomAcc<DT> acc;
+  walk<DT, VEC, kUnroll, NT>(g, acc);
+  block_store_partial(acc, sm, parts + blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// fixed-range histogram pass (Section 4.1)
+// ---------------------------------------------------------------------------
+template <int DT, bool VEC, bool NT>
+__global__ __launch_bounds__(1024) void k_hist(Geom g, float lo, float hi, float scale, int32_t nbins,
+                                               uint32_t rshift, uint64_t* __restrict__ counts,
+                                               uint64_t* __restrict__ outl) {
+  extern __shared__ uint32_t lds[];
+  __shared__ uint32_t osm[32];
+  lds_zero(lds, (uint32_t)nbins << rshift);
+  __syncthreads();
+  HistAcc h{lds, lo, hi, scale, nbins - 1, rshift, threadIdx.x & ((1u << rshift) - 1u)};
+  walk<DT, VEC, kUnroll, NT>(g, h);
+  __syncthreads();
+  lds_flush(lds, (uint32_t)nbins, rshift, counts);
+  block_add_outliers(h.below, h.above, outl, osm);
+}
+
+// ---------------------------------------------------------------------------
+// radix selection: level passes over the cube
+// ---------------------------------------------------------------------------
+template <int DT, bool VEC, bool NT>
+__global__ __launch_bounds__(1024) void k_level1(Geom g, uint32_t rshift, uint64_t* __restrict__ hist1) {
+  extern __shared__ uint32_t lds[];
+  lds_zero(lds, (uint32_t)kBins1 << rshift);
+  __syncthreads();
+  Digit1Acc<DT> d{lds, rshift, threadIdx.x & ((1u << rshift) - 1u)};
+  walk<DT, VEC, kUnroll, NT>(g, d);
+  __syncthreads();
+  lds_flush(lds, kBins1, rshift, hist1);
+}
+
+template <int DT, bool VEC, bool NT>
+__global__ __launch_bounds__(1024) void k_level2(Geom g, SelState* __restrict__ st, uint64_t* __restrict__ hist2,
+                                                 uint32_t* __restrict__ cand) {
+  __shared__ uint32_t lds[kBins2];
+  if (st->done) return;
+  lds_zero(lds, kBins2);
+  __syncthreads();
+  Level2Acc<DT> a{lds, st->prefix >> kShift1, st->compact != 0, cand, &st->ncand, st->cand_cap};
+  walk<DT, VEC, kUnroll, NT>(g, a);
+  __syncthreads();
+  lds_flush(lds, kBins2, 0, hist2);
+}
+
+// Level 3 reads the candidate list when level 2 made one, else the cube.
+template <int DT, bool VEC, bool NT>
+__global__ __launch_bounds__(1024) void k_level3(Geom g, SelState* __restrict__ st, uint64_t* __restrict__ hist3,
+                                                 const uint32_t* __restrict__ cand) {
+  __shared__ uint32_t lds[kBins3];
+  if (st->done) return;
+  lds_zero(lds, kBins3);
+  __syncthreads();
+  const uint32_t p2 = st->prefix >> kShift2;
+  if (st->compact) {
+    const uint32_t n = min(st->ncand, st->cand_cap);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+      const uint32_t key = cand[i];
+      if ((key >> kShift2) == p2) lds_inc(lds, key & 0xFFu);
+    }
+  } else {
+    Level3Acc<DT> a{lds, p2};
+    walk<DT, VEC, kUnroll, NT>(g, a);
+  }
+  __syncthreads();
+  lds_flush(lds, kBins3, 0, hist3);
+}
+
+// ---------------------------------------------------------------------------
+// one-block epilogues: moments merge and digit selection
+// ---------------------------------------------------------------------------
+
+// Chan et al. pairwise update of (n, mean, M2).
+TSA_DEV void chan_merge(double& na, double& ma, double& qa, double nb, double mb, double qb) {
+  if (nb == 0.0) return;
+  if (na == 0.0) {
+    na = nb;
+    ma = mb;
+    qa = qb;
+    return;
+  }
+  const double n = na + nb;
+  const double d = mb - ma;
+  ma = ma + d * (nb / n);
+  qa = qa + qb + d * d * (na * nb / n);
+  na = n;
+}
+
+TSA_DEV double value_of_key(uint32_t k, int dtype) {
+  return dtype == 0 ? (double)__uint_as_float(f32bits_of_key(k)) : (double)i16_of_key(k);
+}
+
+// (n, mean, M2) of one block partial, in double.
+TSA_DEV void partial_stats(const Partial& p, int dtype, double& n, double& m, double& q) {
+  n = (double)p.n;
+  if (p.n == 0) {
+    m = q = 0.0;
+    return;
+  }
+  if (dtype == 0) {
+    const double S = (double)p.sh + (double)p.sl;
+    const double Q = (double)p.qh + (double)p.ql;
+    m = S / n;
+    q = Q - S * m;
+  } else {
+    // exact n*Q - S^2 in 128-bit integers, then one rounding to double
+    const __int128 num = (__int128)p.qi * (__int128)p.n - (__int128)p.si * (__int128)p.si;
+    const int64_t hi = (int64_t)(num >> 64);
+    const uint64_t lo = (uint64_t)num;
+    const double dnum = (double)hi * 18446744073709551616.0 + (double)lo;
+    m = (double)p.si / n;
+    q = dnum / n;
+  }
+}
+
+struct MergeShared {
+  double n[1024], m[1024], q[1024];
+  uint32_t kmin[1024], kmax[1024];
+};
+
+// Whole block: merge np partials in a fixed order (each thread a strided
+// sequence, then a pairwise tree) and write the moments fields of *out.
+// Returns (in every thread) the global count and min/max keys.
+TSA_DEV void merge_moments(const Partial* __restrict__ parts, int np, int dtype, uint64_t volume, tsa_result* out,
+                           MergeShared& sm, uint64_t& n_out, uint32_t& kmin_out, uint32_t& kmax_out) {
+  const int t = threadIdx.x, bs = blockDim.x;
+  double n = 0.0, m = 0.0, q = 0.0;
+  uint32_t mn = 0xFFFFFFFFu, mx = 0u;
+  for (int i = t; i < np; i += bs) {
+    const Partial p = parts[i];
+    double pn, pm, pq;
+    partial_stats(p, dtype, pn, pm, pq);
+    chan_merge(n, m, q, pn, pm, pq);
+    if (p.n) {
+      mn = min(mn, p.kmin);
+      mx = max(mx, p.kmax);
+    }
+  }
+  sm.n[t] = n;
+  sm.m[t] = m;
+  sm.q[t] = q;
+  sm.kmin[t] = mn;
+  sm.kmax[t] = mx;
+  __syncthreads();
+  for (int s = bs / 2; s > 0; s >>= 1) {
+    if (t < s) {
+      double a = sm.n[t], b = sm.m[t], c = sm.q[t];
+      chan_merge(a, b, c, sm.n[t + s], sm.m[t + s], sm.q[t + s]);
+      sm.n[t] = a;
+      sm.m[t] = b;
+      sm.q[t] = c;
+      sm.kmin[t] = min(sm.kmin[t], sm.kmin[t + s]);
+      sm.kmax[t] = max(sm.kmax[t], sm.kmax[t + s]);
+    }
+    __syncthreads();
+  }
+  const double N = sm.n[0];
+  const uint64_t cnt = (uint64_t)N;
+  n_out = cnt;
+  kmin_out = sm.kmin[0];
+  kmax_out = sm.kmax[0];
+  if (t == 0) {
+    out->count = cnt;
+    out->nan_count = volume - cnt;
+    out->status = TSA_OK;
+    if (cnt == 0) {
+      out->mean = out->m2 = out->std = out->min = out->max = __builtin_nan("");
+    } else {
+      const double vmin = value_of_key(sm.kmin[0], dtype), vmax = value_of_key(sm.kmax[0], dtype);
+      out->min = vmin;
+      out->max = vmax;
+      if (sm.kmin[0] == sm.kmax[0]) {  // every valid voxel holds the same value
+        out->mean = vmin;
+        out->m2 = 0.0;
+        out->std = 0.0;
+      } else {
+        const double m2 = sm.q[0] > 0.0 ? sm.q[0] : 0.0;
+        out->mean = sm.m[0];
+        out->m2 = m2;
+        out->std = sqrt(m2 / N);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(1024) void k_moments_merge(const Partial* __restrict__ parts, int np, int dtype,
+                                                        uint64_t volume, tsa_result* out) {
+  __shared__ MergeShared sm;
+  uint64_t n;
+  uint32_t a, b;
+  merge_moments(parts, np, dtype, volume, out, sm, n, a, b);
+}
+
+struct SelectShared {
+  uint64_t wsum[16];
+  uint32_t found;
+};
+
+// Whole block: choose the digit of the current level from its histogram.
+// Level 1 also fixes n and the rank k = floor((n-1)/2) of the lower median.
+// When the key is complete, writes the median (and, if write_counts, the
+// count fields) to *out.
+TSA_DEV void select_level(int level, const uint64_t* __restrict__ hist, SelState* st, int dtype, uint64_t volume,
+                          tsa_result* out, bool write_counts, SelectShared& sm) {
+  if (st->done) return;
+  const int nb = level == 3 ? kBins3 : kBins1;
+  const int shift = level == 1 ? kShift1 : level == 2 ? kShift2 : 0;
+  const int t = threadIdx.x, bs = blockDim.x;
+  const int per = (nb + bs - 1) / bs;
+  const int b0 = t * per;
+  uint64_t local = 0;
+  for (int i = 0; i < per; ++i)
+    if (b0 + i < nb) local += hist[b0 + i];
+  // block exclusive scan of `local`
+  const int lane = t % kWave, w = t / kWave;
+  uint64_t inc = local;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint64_t y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
+  }
+  if (lane == kWave - 1) sm.wsum[w] = inc;
+  if (t == 0) sm.found = 0;
+  __syncthreads();
+  uint64_t base = inc - local, total = 0;
+  for (int i = 0; i < bs / kWave; ++i) {
+    if (i < w) base += sm.wsum[i];
+    total += sm.wsum[i];
+  }
+  uint64_t n = level == 1 ? total : st->n;
+  if (level == 1 && n == 0) {
+    __syncthreads();
+    if (t == 0) {
+      st->n = 0;
+      st->done = 1;
+      out->median = __builtin_nan("");
+      if (write_counts) {
+        out->count = 0;
+        out->nan_count = volume;
+        out->status = TSA_OK;
+      }
+    }
+    return;
+  }
+  const uint64_t k = level == 1 ? (n - 1) / 2 : st->k;
+  __syncthreads();  // every thread has read st before it changes
+  if (local > 0 && k >= base && k < base + local) {
+    uint64_t cum = base;
+    int d = b0;
+    for (int i = 0; i < per; ++i) {
+      const uint64_t h = (b0 + i < nb) ? hist[b0 + i] : 0;
+      if (k < cum + h) {
+        d = b0 + i;
+        break;
+      }
+      cum += h;
+    }
+    const uint64_t bucket = hist[d];
+    const uint32_t prefix = (level == 1 ? 0u : st->prefix) | ((uint32_t)d << shift);
+    st->n = n;
+    st->k = k - cum;
+    st->bucket_n = bucket;
+    st->prefix = prefix;
+    st->level = level;
+    if (level == 1) st->compact = bucket <= st->cand_cap ? 1u : 0u;
+    const bool complete = level == 3 || (dtype == 1 && level == 2);
+    if (complete) {
+      st->done = 1;
+      st->result_key = prefix;
+      out->median = value_of_key(prefix, dtype);
+      if (write_counts) {
+        out->count = n;
+        out->nan_count = volume - n;
+        out->status = TSA_OK;
+      }
+    }
+    sm.found = 1;
+  }
+  __syncthreads();
+  if (t == 0 && !sm.found) {  // inconsistent histogram: never expected
+    st->done = 1;
+    out->median = __builtin_nan("");
+    out->status = TSA_EDEVICE;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_select(int level, const uint64_t* __restrict__ hist, SelState* st,
+                                                 int dtype, uint64_t volume, tsa_result* out, int write_counts) {
+  __shared__ SelectShared sm;
+  select_level(level, hist, st, dtype, volume, out, write_counts != 0, sm);
+}
+
+// ---------------------------------------------------------------------------
+// fused trio: pass A (moments + digit 1), mid (merge + select 1 + range),
+// pass B (histogram over [min, max] + level 2)
+// ---------------------------------------------------------------------------
+template <int DT>
+struct PassA {
+  MomAcc<DT> mom;
+  Digit1Acc<DT> d1;
+  template <class T>
+  TSA_DEV void operator()(T raw, bool in) {
+    mom(raw, in);
+    d1(raw, in);
+  }
+  TSA_DEV void chunk() {}
+};
+
+template <int DT, bool VEC, bool NT>
+__global__ __launch_bounds__(1024) void k_pass_a(Geom g, uint32_t rshift, Partial* __restrict__ parts,
+                                                 uint64_t* __restrict__ hist1) {
+  extern __shared__ uint32_t lds[];
+  __shared__ MomShared sm;
+  lds_zero(lds, (uint32_t)kBins1 << rshift);
+  __syncthreads();
+  PassA<DT> a{MomAcc<DT>{}, Digit1Acc<DT>{lds, rshift, threadIdx.x & ((1u << rshift) - 1u)}};
+  walk<DT, VEC, kUnroll, NT>(g, a);
+  block_store_partial(a.mom, sm, parts + blockIdx.x);
+  __syncthreads();
+  lds_flush(lds, kBins1, rshift, hist1);
+}
+
+__global__ __launch_bounds__(1024) void k_mid(const Partial* __restrict__ parts, int np, int dtype, uint64_t volume,
+                                              int32_t nbins, const uint64_t* __restrict__ hist1, SelState* st,
+                                              tsa_result* out) {
+  __shared__ MergeShared msm;
+  __shared__ SelectShared ssm;
+  uint64_t n;
+  uint32_t kmin, kmax;
+  merge_moments(parts, np, dtype, volume, out, msm, n, kmin, kmax);
+  if (threadIdx.x == 0) {
+    uint32_t ok = 0;
+    float lo = 0.f, hi = 0.f, scale = 0.f;
+    if (n > 0) {
+      lo = (float)value_of_key(kmin, dtype);
+      hi = (float)value_of_key(kmax, dtype);
+      if (isfinite(lo) && isfinite(hi)) {
+        if (lo == hi) {
+          ok = 1;
+        } else {
+          const float width = hi - lo;
+          if (isfinite(width)) {
+            scale = (float)nbins / width;
+            ok = (isfinite(scale) && scale != 0.0f) ? 1u : 0u;
+          }
+        }
+      }
+    }
+    st->hist_ok = ok;
+    st->lo = lo;
+    st->hi = hi;
+    st->scale = scale;
+    // pass B recomputes M2 about c = fl32(mean) when the values differ (float32 cubes)
+    const double mean = out->mean;
+    const bool von = dtype == 0 && n > 0 && kmin != kmax && isfinite(mean);
+    st->shift = von ? (float)mean : 0.0f;
+    st->var_on = von ? 1u : 0u;
+    st->vscale = von ? var_scale_exp(fmax(fabs((double)hi - (double)(float)mean), fabs((double)lo - (double)(float)mean)))
+                     : 0;
+    out->flags = ok ? 0 : TSA_FLAG_HIST_SKIPPED;
+    out->median = __builtin_nan("");
+  }
+  __syncthreads();
+  select_level(1, hist1, st, dtype, volume, out, false, ssm);
+}
+
+template <int DT>
+struct PassB {
+  HistAcc h;
+  Level2Acc<DT> l2;
+  VarAcc var;
+  bool hist_on, var_on;
+  template <class T>
+  TSA_DEV void operator()(T raw, bool in) {
+    if (hist_on) h(raw, in);
+    l2(raw, in);
+    if constexpr (DT == 0) {
+      if (var_on) var(raw, in);
+    }
+  }
+  TSA_DEV void chunk() {}
+};
+
+template <int DT, bool VEC, bool NT>
+__global__ __launch_bounds__(1024) void k_pass_b(Geom g, int32_t nbins, uint32_t rshift, SelState* __restrict__ st,
+                                                 uint64_t* __restrict__ counts, uint64_t* __restrict__ outl,
+                                                 uint64_t* __restrict__ hist2, uint32_t* __restrict__ cand,
+                                                 Partial* __restrict__ parts2) {
+  extern __shared__ uint32_t lds[];  // [nbins << rshift] histogram, then [kBins2] level-2 digits
+  __shared__ uint32_t osm[32];
+  __shared__ MomShared sm;
+  const uint32_t hsize = (uint32_t)nbins << rshift;
+  uint32_t* l2 = lds + hsize;
+  const bool hist_on = st->hist_ok != 0;
+  const bool sel_on = st->done == 0;
+  const bool var_on = DT == 0 && st->var_on != 0;
+  if (!hist_on && !sel_on && !var_on) return;
+  lds_zero(lds, hsize + kBins2);
+  __syncthreads();
+  PassB<DT> b{HistAcc{lds, st->lo, st->hi, st->scale, nbins - 1, rshift, threadIdx.x & ((1u << rshift) - 1u)},
+              Level2Acc<DT>{l2, sel_on ? (st->prefix >> kShift1) : 0xFFFFFFFFu, sel_on && st->compact != 0, cand,
+                            &st->ncand, st->cand_cap},
+              VarAcc{st->shift, st->vscale}, hist_on, var_on};
+  walk<DT, VEC, kUnroll, NT>(g, b);
+  __syncthreads();
+  if (hist_on) lds_flush(lds, (uint32_t)nbins, rshift, counts);
+  if (sel_on) lds_flush(l2, kBins2, 0, hist2);
+  if (hist_on) block_add_outliers(b.h.below, b.h.above, outl, osm);
+  if (var_on) block_store_var(b.var, sm, parts2 + blockIdx.x);
+}
+
+// M2 about the shift c: M2 = sum (x-c)^2 - n (mean - c)^2, block partials
+// added in a fixed order (strided per thread, then a pairwise tree).
+__global__ __launch_bounds__(1024) void k_var_finish(const Partial* __restrict__ parts2, int np,
+                                                     const SelState* __restrict__ st, tsa_result* out) {
+  __shared__ double sq[1024];
+  if (!st->var_on) return;
+  const int t = threadIdx.x, bs = blockDim.x;
+  double q = 0.0;
+  for (int i = t; i < np; i += bs) q += (double)parts2[i].qh + (double)parts2[i].ql;
+  sq[t] = q;
+  __syncthreads();
+  for (int s2 = bs / 2; s2 > 0; s2 >>= 1) {
+    if (t < s2) sq[t] += sq[t + s2];
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double n = (double)out->count;
+    const double dm = out->mean - (double)st->shift;
+    double m2 = ldexp(sq[0], -2 * st->vscale) - n * dm * dm;
+    if (!(m2 > 0.0)) m2 = 0.0;
+    out->m2 = m2;
+    out->std = sqrt(m2 / n);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side: argument checks, geometry, workspace layout, launches
+// ---------------------------------------------------------------------------
+
+static const Tuning& tuning() {
+  static Tuning t = [] {
+    Tuning x;
+    if (const char* s = getenv("TSA_BLOCK")) x.block = atoi(s);
+    if (const char* s = getenv("TSA_BPC")) x.bpc = atoi(s);
+    if (const char* s = getenv("TSA_NT")) x.nt = atoi(s) != 0;
+    if (const char* s = getenv("TSA_REP")) x.rep_shift = atoi(s);
+    if (x.block != 256 && x.block != 512 && x.block != 1024) x.block = 512;
+    if (x.bpc < 1 || x.bpc > 16) x.bpc = 2;
+    if (x.rep_shift < 0 || x.rep_shift > 3) x.rep_shift = -1;
+    return x;
+  }();
+  return t;
+}
+
+int device_info(DevInfo* out) {
+  static DevInfo cache[64];
+  static bool have[64] = {false};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return TSA_EDEVICE;
+  if (!have[dev]) {
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess) return TSA_EDEVICE;
+    if (strncmp(p.gcnArchName, "gfx950", 6) != 0) return TSA_ENOTSUP;
+    cache[dev].cus = p.multiProcessorCount;
+    cache[dev].lds_per_block = p.sharedMemPerBlock;
+    have[dev] = true;
+  }
+  *out = cache[dev];
+  return TSA_OK;
+}
+
+Magic make_magic(uint32_t d) {
+  uint32_t l = 0;
+  while ((1ull << l) < (uint64_t)d) ++l;
+  Magic g;
+  g.m = (uint32_t)((((1ull << 32) * ((1ull << l) - (uint64_t)d)) / (uint64_t)d) + 1ull);
+  g.s1 = l ? 1u : 0u;
+  g.s2 = l ? l - 1u : 0u;
+  return g;
+}
+
+int check_cube(const tsa_cube* c) {
+  if (!c || !c->data) return TSA_EINVAL;
+  if (c->dtype != TSA_F32 && c->dtype != TSA_I16) return TSA_ENOTSUP;
+  if (c->reserved != 0) return TSA_EINVAL;
+  if (c->nx < 1 || c->ny < 1 || c->nz < 1) return TSA_EINVAL;
+  if (c->nx > (1ll << 31) || c->ny > (1ll << 31) || c->nz > (1ll << 31)) return TSA_EINVAL;
+  const double n = (double)c->nx * (double)c->ny * (double)c->nz;
+  if (n > (double)(1ll << 46)) return TSA_EINVAL;
+  return TSA_OK;
+}
+
+int region_box(const tsa_cube* c, const tsa_region* r, tsa_region* b) {
+  if (!r) {
+    b->x0 = b->y0 = b->z0 = 0;
+    b->x1 = c->nx;
+    b->y1 = c->ny;
+    b->z1 = c->nz;
+    return TSA_OK;
+  }
+  if (r->x0 < 0 || r->y0 < 0 || r->z0 < 0 || r->x1 > c->nx || r->y1 > c->ny || r->z1 > c->nz) return TSA_EINVAL;
+  if (r->x0 >= r->x1 || r->y0 >= r->y1 || r->z0 >= r->z1) return TSA_EINVAL;
+  *b = *r;
+  return TSA_OK;
+}
+
+// Build the walk geometry of box b; tile_units = target vectors per rows tile.
+int make_geom(const tsa_cube* c, const tsa_region& b, uint32_t tile_units, Geom* g, bool* vec, int64_t* volume) {
+  const int64_t esz = c->dtype == TSA_F32 ? 4 : 2;
+  const int64_t epv = 16 / esz;
+  const int64_t lx = b.x1 - b.x0, ly = b.y1 - b.y0, lz = b.z1 - b.z0;
+  *volume = lx * ly * lz;
+  memset(g, 0, sizeof(*g));
+  g->base = c->data;
+  const bool aligned = ((uintptr_t)c->data % 16) == 0;
+  const int64_t e0 = b.x0 + c->nx * (b.y0 + c->ny * b.z0);
+  const bool contig = (lx == c->nx && (ly == c->ny || lz == 1)) || (ly == 1 && lz == 1);
+  if (contig) {
+    g->mode = 0;
+    const int64_t e1 = e0 + *volume;
+    *vec = aligned;
+    if (aligned) {
+      int64_t v0 = (e0 + epv - 1) / epv, v1 = e1 / epv;
+      if (v0 >= v1) {
+        g->v0 = g->v1 = 0;
+        g->h0 = e0;
+        g->h1 = e1;
+        g->t0 = g->t1 = 0;
+      } else {
+        g->v0 = v0;
+        g->v1 = v1;
+        g->h0 = e0;
+        g->h1 = v0 * epv;
+        g->t0 = v1 * epv;
+        g->t1 = e1;
+      }
+    } else {
+      g->v0 = e0;
+      g->v1 = e1;
+    }
+    return TSA_OK;
+  }
+  g->mode = 1;
+  if ((uint64_t)ly * (uint64_t)lz > 0xFFFFFFFFull) return TSA_EINVAL;
+  g->nrows = (uint32_t)(ly * lz);
+  g->ly = (uint32_t)ly;
+  *vec = aligned && (c->nx % epv) == 0;
+  if (*vec) {
+    const int64_t c0 = b.x0 / epv, c1 = (b.x1 + epv - 1) / epv;
+    g->v_origin = (b.x0 / epv) + (c->nx / epv) * (b.y0 + c->ny * b.z0);
+    g->v_ystride = c->nx / epv;
+    g->v_zstride = (c->nx / epv) * c->ny;
+    g->vpr = (uint32_t)(c1 - c0);
+    g->head_skip = (uint32_t)(b.x0 % epv);
+    g->last_valid = (uint32_t)(b.x1 - (c1 - 1) * epv);
+  } else {
+    g->v_origin = e0;
+    g->v_ystride = c->nx;
+    g->v_zstride = c->nx * c->ny;
+    g->vpr = (uint32_t)lx;
+    g->head_skip = 0;
+    g->last_valid = 1;
+  }
+  uint32_t rpt = tile_units / g->vpr;
+  if (rpt < 1) rpt = 1;
+  while ((uint64_t)rpt * g->vpr > (1ull << 30) && rpt > 1) rpt >>= 1;
+  g->rpt = rpt;
+  g->ntiles = (g->nrows + rpt - 1) / rpt;
+  g->ly_m = make_magic(g->ly);
+  g->vpr_m = make_magic(g->vpr);
+  return TSA_OK;
+}
+
+// Blocks for a pass over geometry g.
+static int pass_grid(const Geom& g, bool vec, int block, int maxblocks) {
+  int64_t want;
+  if (g.mode == 0)
+    want = vec ? (g.v1 - g.v0 + (int64_t)block * kUnroll - 1) / ((int64_t)block * kUnroll)
+               : (g.v1 - g.v0 + block - 1) / block;
+  else
+    want = g.ntiles;
+  if (want < 1) want = 1;
+  if (want > maxblocks) want = maxblocks;
+  return (int)want;
+}
+
+// Workspace layout of the single-region calls.
+struct WsLayout {
+  size_t partials, partials2, hist1, hist2, hist3, state, outl, cand, total;
+  uint32_t cand_cap;
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static WsLayout ws_layout(int64_t volume) {
+  WsLayout L;
+  size_t o = 0;
+  L.partials = o;
+  o = align256(o + sizeof(Partial) * kMaxBlocks);
+  L.partials2 = o;
+  o = align256(o + sizeof(Partial) * kMaxBlocks);
+  L.hist1 = o;
+  o = align256(o + 8 * kBins1);
+  L.hist2 = o;
+  o = align256(o + 8 * kBins2);
+  L.hist3 = o;
+  o = align256(o + 8 * kBins3);
+  L.state = o;
+  o = align256(o + sizeof(SelState));
+  L.outl = o;
+  o = align256(o + 16);
+  int64_t cap = volume / 64;
+  if (cap < 65536) cap = 65536;
+  if (cap > (1ll << 26)) cap = 1ll << 26;
+  if (cap > volume) cap = volume;
+  L.cand_cap = (uint32_t)cap;
+  L.cand = o;
+  o = align256(o + 4 * (size_t)cap);
+  L.total = o;
+  return L;
+}
+
+size_t single_ws_bytes(int64_t volume) { return ws_layout(volume).total; }
+
+static int launch_ok() { return hipGetLastError() == hipSuccess ? TSA_OK : TSA_EDEVICE; }
+
+static void fill32(void* p, size_t words, uint32_t v, hipStream_t s) {
+  if (words == 0) return;
+  int blocks = (int)((words + 255) / 256);
+  if (blocks > 1024) blocks = 1024;
+  TSA_TRACED("fill", s, hipLaunchKernelGGL(k_fill32, dim3(blocks), dim3(256), 0, s, (uint32_t*)p, (uint64_t)words, v));
+}
+
+#define TSA_DISPATCH(DTV, VECV, NTV, EXPR)                              \
+  do {                                                                  \
+    if ((DTV) == 0 && (VECV) && (NTV)) {                                \
+      constexpr int DT = 0;                                             \
+      constexpr bool VEC = true, NT = true;                             \
+      EXPR;                                                             \
+    } else if ((DTV) == 0 && (VECV) && !(NTV)) {                        \
+      constexpr int DT = 0;                                             \
+      constexpr bool VEC = true, NT = false;                            \
+      EXPR;                                                             \
+    } else if ((DTV) == 0 && !(VECV)) {                                 \
+      constexpr int DT = 0;                                             \
+      constexpr bool VEC = false, NT = false;                           \
+      EXPR;                                                             \
+    } else if ((DTV) == 1 && (VECV) && (NTV)) {                         \
+      constexpr int DT = 1;                                             \
+      constexpr bool VEC = true, NT = true;                             \
+      EXPR;                                                             \
+    } else if ((DTV) == 1 && (VECV) && !(NTV)) {                        \
+      constexpr int DT = 1;                                             \
+      constexpr bool VEC = true, NT = false;                            \
+      EXPR;                                                             \
+    } else {                                                            \
+      constexpr int DT = 1;                                             \
+      constexpr bool VEC = false, NT = false;                           \
+      EXPR;                                                             \
+    }                                                                   \
+  } while (0)
+
+// Common preparation of a single-region call.
+struct Prep {
+  DevInfo dev;
+  tsa_region box;
+  Geom g;
+  bool vec;
+  int64_t volume;
+  WsLayout L;
+  char* ws;
+  hipStream_t s;
+  int block, grid;
+};
+
+static int prepare(const tsa_cube* cube, const tsa_region* region, void* d_ws, size_t ws_bytes,
+                   tsa_stream_t stream, Prep* P) {
+  int st = check_cube(cube);
+  if (st) return st;
+  if ((st = region_box(cube, region, &P->box))) return st;
+  if ((st = device_info(&P->dev))) return st;
+  if ((st = make_geom(cube, P->box, kTileUnits, &P->g, &P->vec, &P->volume))) return st;
+  P->L = ws_layout(P->volume);
+  if (!d_ws || ws_bytes < P->L.total) return TSA_ENOMEM;
+  P->ws = (char*)d_ws;
+  P->s = (hipStream_t)stream;
+  const Tuning& T = tuning();
+  P->block = T.block;
+  int maxb = P->dev.cus * T.bpc;
+  if (maxb > kMaxBlocks) maxb = kMaxBlocks;
+  P->grid = pass_grid(P->g, P->vec, P->block, maxb);
+  return TSA_OK;
+}
+
+static uint32_t rep_shift_for(int nbins, size_t lds_budget) {
+  const Tuning& T = tuning();
+  uint32_t r = 0;
+  if (T.rep_shift >= 0)
+    r = (uint32_t)T.rep_shift;
+  else
+    r = nbins <= 1024 ? 2u : nbins <= 4096 ? 1u : 0u;
+  while (r > 0 && ((size_t)nbins << r) * 4 > lds_budget) --r;
+  return r;
+}
+
+// Zero the level histograms and the selection state, then set the capacity.
+static void reset_select(const Prep& P) {
+  fill32(P.ws + P.L.hist1, (P.L.state + sizeof(SelState) - P.L.hist1) / 4, 0u, P.s);
+  // cand_cap is set by a one-element fill at its offset
+  fill32(P.ws + P.L.state + offsetof(SelState, cand_cap), 1, P.L.cand_cap, P.s);
+}
+
+int run_moments(const tsa_cube* cube, const tsa_region* region, tsa_result* d_out, void* d_ws, size_t ws_bytes,
+                tsa_stream_t stream) {
+  if (!d_out) return TSA_EINVAL;
+  Prep P;
+  int st = prepare(cube, region, d_ws, ws_bytes, stream, &P);
+  if (st) return st;
+  Partial* parts = (Partial*)(P.ws + P.L.partials);
+  TSA_TRACED("moments", P.s,
+    TSA_DISPATCH(cube->dtype, P.vec, tuning().nt,
+                 hipLaunchKernelGGL((k_moments<DT, VEC, NT>), dim3(P.grid), dim3(P.block), 0, P.s, P.g, parts)));
+  TSA_TRACED("moments_merge", P.s,
+             hipLaunchKernelGGL(k_moments_merge, dim3(1), dim3(1024), 0, P.s, parts, P.grid, cube->dtype,
+                                (uint64_t)P.volume, d_out));
+  return launch_ok();
+}
+
+int run_histogram(const tsa_cube* cube, const tsa_region* region, float lo, float hi, int32_t nbins,
+                  uint64_t* d_counts, uint64_t* d_outliers, void* d_ws, size_t ws_bytes, tsa_stream_t stream) {
+  if (!d_counts) return TSA_EINVAL;
+  if (nbins < 1 || nbins > 65536) return TSA_EINVAL;
+  if (!isfinite(lo) || !isfinite(hi) || lo > hi) return TSA_EINVAL;
+  float scale = 0.0f;
+  if (lo < hi) {
+    volatile float width = hi - lo;
+    if (!isfinite(width)) return TSA_EINVAL;
+    volatile float sc = (float)nbins / width;
+    if (!isfinite(sc) || sc == 0.0f) return TSA_EINVAL;
+    scale = sc;
+  }
+  Prep P;
+  int st = prepare(cube, region, d_ws, ws_bytes, stream, &P);
+  if (st) return st;
+  uint64_t* outl = d_outliers ? d_outliers : (uint64_t*)(P.ws + P.L.outl);
+  fill32(d_counts, (size_t)nbins * 2, 0u, P.s);
+  fill32(outl, 4, 0u, P.s);
+  const size_t budget = P.dev.lds_per_block < 65536 ? P.dev.lds_per_block : 65536;
+  const uint32_t rs = rep_shift_for(nbins, budget);
+  const size_t lds = ((size_t)nbins << rs) * 4;
+  if (lds <= budget) {
+    TSA_TRACED("hist", P.s,
+    TSA_DISPATCH(cube->dtype, P.vec, tuning().nt,
+                   hipLaunchKernelGGL((k_hist<DT, VEC, NT>), dim3(P.grid), dim3(P.block), lds, P.s, P.g, lo, hi, scale,
+                                      nbins, rs, d_counts, outl)));
+    return launch_ok();
+  }
+  return run_histogram_wide(cube, P.g, P.vec, P.grid, P.block, lo, hi, scale, nbins, d_counts, outl, P.s);
+}
+
+static int launch_median_tail(const tsa_cube* cube, const Prep& P, tsa_result* d_out, bool write_counts) {
+  SelState* stp = (SelState*)(P.ws + P.L.state);
+  uint64_t* h2 = (uint64_t*)(P.ws + P.L.hist2);
+  uint64_t* h3 = (uint64_t*)(P.ws + P.L.hist3);
+  uint32_t* cand = (uint32_t*)(P.ws + P.L.cand);
+  TSA_TRACED("select", P.s,
+             hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, P.s, 2, (const uint64_t*)h2, stp, cube->dtype,
+                                (uint64_t)P.volume, d_out, (int)write_counts));
+  TSA_TRACED("level3", P.s,
+    TSA_DISPATCH(cube->dtype, P.vec, tuning().nt,
+                 hipLaunchKernelGGL((k_level3<DT, VEC, NT>), dim3(P.grid), dim3(P.block), 0, P.s, P.g, stp, h3,
+                                    (const uint32_t*)cand)));
+  TSA_TRACED("select", P.s,
+             hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, P.s, 3, (const uint64_t*)h3, stp, cube->dtype,
+                                (uint64_t)P.volume, d_out, (int)write_counts));
+  return launch_ok();
+}
+
+int run_median(const tsa_cube* cube, const tsa_region* region, tsa_result* d_out, void* d_ws, size_t ws_bytes,
+               tsa_stream_t stream) {
+  if (!d_out) return TSA_EINVAL;
+  Prep P;
+  int st = prepare(cube, region, d_ws, ws_bytes, stream, &P);
+  if (st) return st;
+  reset_select(P);
+  SelState* stp = (SelState*)(P.ws + P.L.state);
+  uint64_t* h1 = (uint64_t*)(P.ws + P.L.hist1);
+  uint64_t* h2 = (uint64_t*)(P.ws + P.L.hist2);
+  uint32_t* cand = (uint32_t*)(P.ws + P.L.cand);
+  const uint32_t rs = rep_shift_for(kBins1, 32768);
+  TSA_TRACED("level1", P.s,
+    TSA_DISPATCH(cube->dtype, P.vec, tuning().nt,
+                 hipLaunchKernelGGL((k_level1<DT, VEC, NT>), dim3(P.grid), dim3(P.block), ((size_t)kBins1 << rs) * 4,
+                                    P.s, P.g, rs, h1)));
+  TSA_TRACED("select", P.s,
+             hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, P.s, 1, (const uint64_t*)h1, stp, cube->dtype,
+                                (uint64_t)P.volume, d_out, 1));
+  TSA_TRACED("level2", P.s,
+    TSA_DISPATCH(cube->dtype, P.vec, tuning().nt,
+                 hipLaunchKernelGGL((k_level2<DT, VEC, NT>), dim3(P.grid), dim3(P.block), 0, P.s, P.g, stp, h2, cand)));
+  return launch_median_tail(cube, P, d_out, true);
+}
+
+int run_stats(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa_result* d_out, uint64_t* d_counts,
+              uint64_t* d_outliers, void* d_ws, size_t ws_bytes, tsa_stream_t stream) {
+  if (!d_out || !d_counts) return TSA_EINVAL;
+  if (nbins < 1 || nbins > 65536) return TSA_EINVAL;
+  Prep P;
+  int st = prepare(cube, region, d_ws, ws_bytes, stream, &P);
+  if (st) return st;
+  const size_t budget = P.dev.lds_per_block < 65536 ? P.dev.lds_per_block : 65536;
+  if ((size_t)nbins * 4 + kBins2 * 4 > budget) return TSA_ENOTSUP;
+  reset_select(P);
+  uint64_t* outl = d_outliers ? d_outliers : (uint64_t*)(P.ws + P.L.outl);
+  fill32(d_counts, (size_t)nbins * 2, 0u, P.s);
+  fill32(outl, 4, 0u, P.s);
+  Partial* parts = (Partial*)(P.ws + P.L.partials);
+  SelState* stp = (SelState*)(P.ws + P.L.state);
+  uint64_t* h1 = (uint64_t*)(P.ws + P.L.hist1);
+  uint64_t* h2 = (uint64_t*)(P.ws + P.L.hist2);
+  uint32_t* cand = (uint32_t*)(P.ws + P.L.cand);
+  const uint32_t rs1 = rep_shift_for(kBins1, 32768);
+  TSA_TRACED("pass_a", P.s,
+    TSA_DISPATCH(cube->dtype, P.vec, tuning().nt,
+                 hipLaunchKernelGGL((k_pass_a<DT, VEC, NT>), dim3(P.grid), dim3(P.block), ((size_t)kBins1 << rs1) * 4,
+                                    P.s, P.g, rs1, parts, h1)));
+  TSA_TRACED("mid", P.s,
+             hipLaunchKernelGGL(k_mid, dim3(1), dim3(1024), 0, P.s, (const Partial*)parts, P.grid, cube->dtype,
+                                (uint64_t)P.volume, nbins, (const uint64_t*)h1, stp, d_out));
+  uint32_t rsb = rep_shift_for(nbins, budget - kBins2 * 4);
+  const size_t ldsb = ((size_t)nbins << rsb) * 4 + kBins2 * 4;
+  Partial* parts2 = (Partial*)(P.ws + P.L.partials2);
+  TSA_TRACED("pass_b", P.s,
+    TSA_DISPATCH(cube->dtype, P.vec, tuning().nt,
+                 hipLaunchKernelGGL((k_pass_b<DT, VEC, NT>), dim3(P.grid), dim3(P.block), ldsb, P.s, P.g, nbins, rsb,
+                                    stp, d_counts, outl, h2, cand, parts2)));
+  TSA_TRACED("var_finish", P.s,
+             hipLaunchKernelGGL(k_var_finish, dim3(1), dim3(1024), 0, P.s, (const Partial*)parts2, P.grid,
+                                (const SelState*)stp, d_out));
+  return launch_median_tail(cube, P, d_out, false);
+}
+
+}  // namespace tsa

@@ -1,0 +1,349 @@
+// Per-element accumulators and block-level epilogues shared by the kernels.
+#pragma once
+
+#include <climits>
+
+#include "tsa_device.hpp"
+
+namespace tsa {
+
+// ---- validity and key of one element ---------------------------------------
+template <int DT>
+struct Elt;
+template <>
+struct Elt<0> {
+  TSA_DEV static bool valid(float x, bool in) { return in && (x == x); }
+  TSA_DEV static uint32_t key(float x) { return key_f32(__float_as_uint(x)); }
+  TSA_DEV static float val(float x) { return x; }
+};
+template <>
+struct Elt<1> {
+  TSA_DEV static bool valid(int16_t, bool in) { return in; }
+  TSA_DEV static uint32_t key(int16_t x) { return key_i16(x); }
+  TSA_DEV static float val(int16_t x) { return (float)x; }
+};
+
+// ---- moments (Section 4.2): count, min/max keys, sum and sum of squares -------
+// float32: each lane keeps sum x and sum x^2 as an unevaluated float pair
+// (hi + lo).  Every addition is split exactly by TwoSum; the rounding error
+// goes to lo.  x^2 is split exactly by an FMA.  NaN and masked lanes add 0.
+template <int DT>
+struct MomAcc;
+
+template <>
+struct MomAcc<0> {
+  float sh = 0.f, sl = 0.f, qh = 0.f, ql = 0.f;
+  uint32_t kmin = 0xFFFFFFFFu, kmax = 0u, cnt = 0u;
+  TSA_DEV void operator()(float x, bool in) {
+    const bool ok = Elt<0>::valid(x, in);
+    const float v = ok ? x : 0.0f;
+    float s, e;
+    two_sum(sh, v, s, e);
+    sh = s;
+    sl += e;
+    const float p = v * v;
+    const float pe = __builtin_fmaf(v, v, -p);
+    float q, eq;
+    two_sum(qh, p, q, eq);
+    qh = q;
+    ql += eq + pe;
+    const uint32_t k = Elt<0>::key(x);
+    kmin = min(kmin, ok ? k : 0xFFFFFFFFu);
+    kmax = max(kmax, ok ? k : 0u);
+    cnt += ok ? 1u : 0u;
+  }
+  TSA_DEV void chunk() {}
+};
+
+// int16: exact integer sums (|x| <= 32768, x^2 <= 2^30).
+template <>
+struct MomAcc<1> {
+  int64_t s = 0;
+  uint64_t q = 0;
+  uint32_t kmin = 0xFFFFFFFFu, kmax = 0u, cnt = 0u;
+  TSA_DEV void operator()(int16_t x, bool in) {
+    const int32_t v = in ? (int32_t)x : 0;
+    s += v;
+    q += (uint32_t)(v * v);
+    const uint32_t k = key_i16(x);
+    kmin = min(kmin, in ? k : 0xFFFFFFFFu);
+    kmax = max(kmax, in ? k : 0u);
+    cnt += in ? 1u : 0u;
+  }
+  TSA_DEV void chunk() {}
+};
+
+// Reduce a block's lanes (fixed order) and store one Partial.
+struct alignas(16) MomShared {
+  float sh[16], sl[16], qh[16], ql[16];
+  int64_t si[16];
+  uint64_t qi[16];
+  uint32_t kmin[16], kmax[16];
+  uint64_t cnt[16];
+};
+
+TSA_DEV void block_store_partial(MomAcc<0>& a, MomShared& sm, Partial* out) {
+  float h, l;
+  two_sum(a.sh, a.sl, h, l);
+  a.sh = h;
+  a.sl = l;
+  two_sum(a.qh, a.ql, h, l);
+  a.qh = h;
+  a.ql = l;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const float bsh = __shfl_xor(a.sh, o), bsl = __shfl_xor(a.sl, o);
+    const float bqh = __shfl_xor(a.qh, o), bql = __shfl_xor(a.ql, o);
+    dw_add(a.sh, a.sl, bsh, bsl);
+    dw_add(a.qh, a.ql, bqh, bql);
+  }
+  const uint32_t kmin = wave_min_u32(a.kmin), kmax = wave_max_u32(a.kmax);
+  const uint64_t cnt = wave_sum_u64(a.cnt);
+  const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  if (lane == 0) {
+    sm.sh[w] = a.sh;
+    sm.sl[w] = a.sl;
+    sm.qh[w] = a.qh;
+    sm.ql[w] = a.ql;
+    sm.kmin[w] = kmin;
+    sm.kmax[w] = kmax;
+    sm.cnt[w] = cnt;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = blockDim.x / kWave;
+    float sh = sm.sh[0], sl = sm.sl[0], qh = sm.qh[0], ql = sm.ql[0];
+    uint32_t mn = sm.kmin[0], mx = sm.kmax[0];
+    uint64_t n = sm.cnt[0];
+    for (int i = 1; i < nw; ++i) {
+      dw_add(sh, sl, sm.sh[i], sm.sl[i]);
+      dw_add(qh, ql, sm.qh[i], sm.ql[i]);
+      mn = min(mn, sm.kmin[i]);
+      mx = max(mx, sm.kmax[i]);
+      n += sm.cnt[i];
+    }
+    Partial p;
+    p.n = n;
+    p.kmin = mn;
+    p.kmax = mx;
+    p.sh = sh;
+    p.sl = sl;
+    p.qh = qh;
+    p.ql = ql;
+    p.si = 0;
+    p.qi = 0;
+    *out = p;
+  }
+}
+
+TSA_DEV void block_store_partial(MomAcc<1>& a, MomShared& sm, Partial* out) {
+  const int64_t s = wave_sum_i64(a.s);
+  const uint64_t q = wave_sum_u64(a.q);
+  const uint32_t kmin = wave_min_u32(a.kmin), kmax = wave_max_u32(a.kmax);
+  const uint64_t cnt = wave_sum_u64(a.cnt);
+  const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  if (lane == 0) {
+    sm.si[w] = s;
+    sm.qi[w] = q;
+    sm.kmin[w] = kmin;
+    sm.kmax[w] = kmax;
+    sm.cnt[w] = cnt;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = blockDim.x / kWave;
+    Partial p;
+    p.n = 0;
+    p.si = 0;
+    p.qi = 0;
+    p.kmin = 0xFFFFFFFFu;
+    p.kmax = 0u;
+    for (int i = 0; i < nw; ++i) {
+      p.si += sm.si[i];
+      p.qi += sm.qi[i];
+      p.kmin = min(p.kmin, sm.kmin[i]);
+      p.kmax = max(p.kmax, sm.kmax[i]);
+      p.n += sm.cnt[i];
+    }
+    p.sh = p.sl = p.qh = p.ql = 0.f;
+    *out = p;
+  }
+}
+
+// ---- second moment about a shift (two-pass form, fused path) ----------------
+// sum (x - c)^2 with x - c split exactly into d + e by TwoSum, so the squares
+// carry no cancellation however large the mean is against the spread; d and e
+// are scaled by a power of two chosen from the data's extent, so the squares
+// stay inside the float range for denormal and for huge values alike.
+struct VarAcc {
+  float c;
+  int32_t sc;  // deviations are scaled by 2^sc (exact) so their squares neither overflow nor underflow
+  float qh = 0.f, ql = 0.f;
+  TSA_DEV void operator()(float x, bool in) {
+    const bool ok = in && (x == x);
+    float d, e;
+    two_sum(ok ? x : c, -c, d, e);  // masked lanes: d = e = 0
+    d = __builtin_amdgcn_ldexpf(d, sc);
+    e = __builtin_amdgcn_ldexpf(e, sc);
+    const float p = d * d;
+    const float pe = __builtin_fmaf(d, d, -p);
+    float q, eq;
+    two_sum(qh, p, q, eq);
+    qh = q;
+    ql += eq + __builtin_fmaf(2.0f * d, e, pe);
+  }
+  TSA_DEV void chunk() {}
+};
+
+TSA_DEV void block_store_var(VarAcc& a, MomShared& sm, Partial* out) {
+  float h, l;
+  two_sum(a.qh, a.ql, h, l);
+  a.qh = h;
+  a.ql = l;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const float bqh = __shfl_xor(a.qh, o), bql = __shfl_xor(a.ql, o);
+    dw_add(a.qh, a.ql, bqh, bql);
+  }
+  const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  if (lane == 0) {
+    sm.qh[w] = a.qh;
+    sm.ql[w] = a.ql;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = blockDim.x / kWave;
+    float qh = sm.qh[0], ql = sm.ql[0];
+    for (int i = 1; i < nw; ++i) dw_add(qh, ql, sm.qh[i], sm.ql[i]);
+    Partial p;
+    p.n = 0;
+    p.kmin = p.kmax = 0;
+    p.sh = p.sl = 0.f;
+    p.qh = qh;
+    p.ql = ql;
+    p.si = 0;
+    p.qi = 0;
+    *out = p;
+  }
+}
+
+// ---- LDS-privatised counters -------------------------------------------------
+// Bin b, replica r lives at lds[(b << rshift) + r]; a lane uses replica
+// (lane & (R-1)) so lanes of one wave that hit the same bin mostly touch
+// different words.
+TSA_DEV void lds_inc(uint32_t* lds, uint32_t idx) {
+  __hip_atomic_fetch_add(lds + idx, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+TSA_DEV void lds_zero(uint32_t* lds, uint32_t n) {
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) lds[i] = 0u;
+}
+
+// Sum the replicas of each bin and add the non-zero ones to global counters.
+TSA_DEV void lds_flush(const uint32_t* lds, uint32_t nbins, uint32_t rshift, uint64_t* g) {
+  const uint32_t R = 1u << rshift;
+  for (uint32_t b = threadIdx.x; b < nbins; b += blockDim.x) {
+    uint32_t c = 0;
+    for (uint32_t r = 0; r < R; ++r) c += lds[(b << rshift) + r];
+    if (c) atomicAdd((unsigned long long*)(g + b), (unsigned long long)c);
+  }
+}
+
+// ---- histogram (Section 4.1) ---------------------------------------------------
+struct HistAcc {
+  uint32_t* lds;
+  float lo, hi, scale;
+  int32_t nbm1;
+  uint32_t rshift, rep;
+  uint32_t below = 0, above = 0;
+  template <class T>
+  TSA_DEV void operator()(T raw, bool in) {
+    const float v = (float)raw;  // exact for int16
+    below += (in && v < lo) ? 1u : 0u;
+    above += (in && v > hi) ? 1u : 0u;
+    if (in && v >= lo && v <= hi) {  // NaN fails both tests
+      const float d = v - lo;
+      const float t = d * scale;  // lo == hi: scale == 0 and t == 0
+      const int32_t b = min(max((int32_t)t, 0), nbm1);
+      lds_inc(lds, ((uint32_t)b << rshift) + rep);
+    }
+  }
+  TSA_DEV void chunk() {}
+};
+
+TSA_DEV void block_add_outliers(uint32_t below, uint32_t above, uint64_t* g, uint32_t* sm) {
+  below = wave_sum_u32(below);
+  above = wave_sum_u32(above);
+  const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  if (lane == 0) {
+    sm[2 * w] = below;
+    sm[2 * w + 1] = above;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t b = 0, a = 0;
+    for (int i = 0; i < (int)(blockDim.x / kWave); ++i) {
+      b += sm[2 * i];
+      a += sm[2 * i + 1];
+    }
+    if (b) atomicAdd((unsigned long long*)g, (unsigned long long)b);
+    if (a) atomicAdd((unsigned long long*)(g + 1), (unsigned long long)a);
+  }
+}
+
+// ---- radix digits of the key (Section 4.3 replaced by radix selection) --------
+template <int DT>
+struct Digit1Acc {  // top 12 key bits of every valid element
+  uint32_t* lds;
+  uint32_t rshift, rep;
+  template <class T>
+  TSA_DEV void operator()(T raw, bool in) {
+    if (Elt<DT>::valid(raw, in)) lds_inc(lds, ((Elt<DT>::key(raw) >> kShift1) << rshift) + rep);
+  }
+  TSA_DEV void chunk() {}
+};
+
+// Append the lanes' keys whose flag is set to a global list (one atomic per wave).
+TSA_DEV void wave_append(bool m, uint32_t key, uint32_t* list, uint32_t* counter, uint32_t cap) {
+  const uint64_t bal = __ballot(m);
+  if (bal == 0) return;
+  const int lane = threadIdx.x % kWave;
+  const int leader = __ffsll((unsigned long long)bal) - 1;
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(bal));
+  base = __shfl(base, leader);
+  const uint32_t off = (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+  if (m && base + off < cap) list[base + off] = key;
+}
+
+template <int DT>
+struct Level2Acc {  // keys inside the level-1 bucket: next 12 bits, optional copy
+  uint32_t* lds;
+  uint32_t p1;
+  bool compact;
+  uint32_t* cand;
+  uint32_t* ncand;
+  uint32_t cap;
+  template <class T>
+  TSA_DEV void operator()(T raw, bool in) {
+    const uint32_t key = Elt<DT>::key(raw);
+    const bool m = Elt<DT>::valid(raw, in) && (key >> kShift1) == p1;
+    if (m) lds_inc(lds, (key >> kShift2) & 0xFFFu);
+    if (compact) wave_append(m, key, cand, ncand, cap);
+  }
+  TSA_DEV void chunk() {}
+};
+
+template <int DT>
+struct Level3Acc {  // keys inside the level-2 bucket: last 8 bits
+  uint32_t* lds;
+  uint32_t p2;
+  template <class T>
+  TSA_DEV void operator()(T raw, bool in) {
+    const uint32_t key = Elt<DT>::key(raw);
+    if (Elt<DT>::valid(raw, in) && (key >> kShift2) == p2) lds_inc(lds, key & 0xFFu);
+  }
+  TSA_DEV void chunk() {}
+};
+
+}  // namespace tsa

@@ -1,0 +1,161 @@
+// Visiting the voxels of a cube or of a box inside it, 16 bytes per lane.
+//
+// Two shapes of work:
+//  * contiguous: the box is one run of memory (whole cube, whole planes, one
+//    row).  Blocks stride over 16-byte vectors; U vector loads are issued per
+//    lane before any is consumed, so each CU keeps many bytes in flight.  The
+//    few elements before the first and after the last aligned vector are
+//    visited one by one by block 0.
+//  * rows: a general box is ly*lz rows of lx elements.  Rows are grouped into
+//    tiles; a block flattens its tile's (row, vector) pairs so that narrow
+//    boxes still fill every lane.  Row starts share one alignment offset
+//    (nx is a multiple of the vector width), so the first and last vector of
+//    every row carry the same element masks.
+#pragma once
+
+#include "tsa_device.hpp"
+
+namespace tsa {
+
+struct Geom {
+  const void* base;
+  int32_t mode;  // 0 contiguous, 1 rows
+  int32_t pad0;
+  // contiguous: vectors [v0, v1) plus single elements [h0, h1) and [t0, t1)
+  int64_t v0, v1, h0, h1, t0, t1;
+  // rows: units are vectors (or elements on the scalar path)
+  int64_t v_origin, v_ystride, v_zstride;
+  uint32_t ly, nrows, vpr, rpt, ntiles;
+  uint32_t head_skip, last_valid;
+  uint32_t pad1;
+  Magic ly_m, vpr_m;
+};
+
+// Rows [r0, r0 + nr) of a box (row r is y = r % ly, z = r / ly inside the
+// box), flattened over (row, vector) so narrow rows still fill the lanes.
+template <int DT, bool VEC, int U, bool NT, class F>
+TSA_DEV void walk_rows(const void* base, int64_t v_origin, int64_t v_ystride, int64_t v_zstride, uint32_t ly,
+                       const Magic& ly_m, uint32_t vpr, const Magic& vpr_m, uint32_t head_skip, uint32_t last_valid,
+                       uint32_t r0, uint32_t nr, F& f) {
+  using TT = Ty<DT>;
+  using T = typename TT::T;
+  const uint32_t bs = blockDim.x;
+  const uint32_t cnt = nr * vpr;
+  for (uint32_t li0 = 0; li0 < cnt; li0 += bs * U) {
+    if constexpr (VEC) {
+      const uint4* vb = (const uint4*)base;
+      uint4 r[U];
+      uint32_t jj[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t li = li0 + u * bs + threadIdx.x;
+        jj[u] = 0xFFFFFFFFu;
+        if (li < cnt) {
+          const uint32_t lr = mdiv(li, vpr_m);
+          const uint32_t j = li - lr * vpr;
+          const uint32_t row = r0 + lr;
+          const uint32_t rz = mdiv(row, ly_m);
+          const uint32_t ry = row - rz * ly;
+          const int64_t vi = v_origin + (int64_t)rz * v_zstride + (int64_t)ry * v_ystride + j;
+          r[u] = load16<NT>(vb + vi);
+          jj[u] = j;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (jj[u] != 0xFFFFFFFFu) {
+          const bool first = jj[u] == 0, last = jj[u] == vpr - 1;
+#pragma unroll
+          for (int e = 0; e < TT::EPV; ++e) {
+            const bool in = (!first || (uint32_t)e >= head_skip) && (!last || (uint32_t)e < last_valid);
+            f(TT::get(r[u], e), in);
+          }
+        }
+      }
+    } else {
+      const T* sb = (const T*)base;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t li = li0 + u * bs + threadIdx.x;
+        if (li < cnt) {
+          const uint32_t lr = mdiv(li, vpr_m);
+          const uint32_t j = li - lr * vpr;
+          const uint32_t row = r0 + lr;
+          const uint32_t rz = mdiv(row, ly_m);
+          const uint32_t ry = row - rz * ly;
+          const int64_t ei = v_origin + (int64_t)rz * v_zstride + (int64_t)ry * v_ystride + j;
+          f(sb[ei], true);
+        }
+      }
+    }
+    f.chunk();
+  }
+}
+
+// f(T value, bool in_box) is called once per element; in_box is false only
+// for the masked lanes of the first/last vector of a row.  f.chunk() is
+// called by every thread of the block at the same points, after at most
+// blockDim.x * U vectors have been visited since the previous call, so it may
+// synchronise the block.
+template <int DT, bool VEC, int U, bool NT, class F>
+TSA_DEV void walk(const Geom& g, F& f) {
+  using TT = Ty<DT>;
+  using T = typename TT::T;
+  const T* sb = (const T*)g.base;
+  const int64_t bs = blockDim.x;
+  if (g.mode == 0) {
+    if constexpr (VEC) {
+      const uint4* vb = (const uint4*)g.base;
+      const int64_t chunk = bs * U;
+      const int64_t stride = chunk * gridDim.x;
+      for (int64_t cb = g.v0 + (int64_t)blockIdx.x * chunk; cb < g.v1; cb += stride) {
+        const int64_t i = cb + threadIdx.x;
+        if (cb + chunk <= g.v1) {
+          uint4 r[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) r[u] = load16<NT>(vb + i + u * bs);
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int e = 0; e < TT::EPV; ++e) f(TT::get(r[u], e), true);
+          }
+        } else {
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int64_t j = i + u * bs;
+            if (j < g.v1) {
+              uint4 r = load16<NT>(vb + j);
+#pragma unroll
+              for (int e = 0; e < TT::EPV; ++e) f(TT::get(r, e), true);
+            }
+          }
+        }
+        f.chunk();
+      }
+      if (blockIdx.x == 0) {
+        for (int64_t e = g.h0 + threadIdx.x; e < g.h1; e += bs) f(sb[e], true);
+        for (int64_t e = g.t0 + threadIdx.x; e < g.t1; e += bs) f(sb[e], true);
+      }
+    } else {
+      const int64_t chunk = bs * U;
+      const int64_t stride = chunk * gridDim.x;
+      for (int64_t cb = g.v0 + (int64_t)blockIdx.x * chunk; cb < g.v1; cb += stride) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t j = cb + u * bs + threadIdx.x;
+          if (j < g.v1) f(sb[j], true);
+        }
+        f.chunk();
+      }
+    }
+    return;
+  }
+  // rows
+  for (uint32_t t = blockIdx.x; t < g.ntiles; t += gridDim.x) {
+    const uint32_t r0 = t * g.rpt;
+    walk_rows<DT, VEC, U, NT>(g.base, g.v_origin, g.v_ystride, g.v_zstride, g.ly, g.ly_m, g.vpr, g.vpr_m,
+                              g.head_skip, g.last_valid, r0, min(g.rpt, g.nrows - r0), f);
+  }
+}
+
+}  // namespace tsa

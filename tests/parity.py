@@ -1,0 +1,68 @@
+"""Comparison helpers for GPU-vs-oracle parity tests.
+
+Tolerances:
+* counts, nan_count, histogram bins, outliers, min, max, median: bit-exact;
+* mean: |gpu - oracle| <= 1e-12 |oracle| + 1e-14 rms(x)   (rms = hypot(mean, std));
+  the second term only matters when the mean is ~0 relative to the spread,
+  where a relative bound on the mean is meaningless.  Float-float sums carry
+  ~2^-44 relative error of sum |x|, i.e. well below 1e-14 rms;
+* std and m2: relative 1e-12 (exactly 0 when the oracle's is 0).
+"""
+import math
+import struct
+
+import numpy as np
+
+MEAN_REL = 1e-12
+MEAN_RMS = 1e-14
+STD_REL = 1e-12
+
+
+def f32_bits(v: float) -> bytes:
+    return struct.pack("<f", v)
+
+
+def same_value(a: float, b: float, dtype: str = "f32") -> bool:
+    """Bit-exact equality of two stored values (NaN == NaN)."""
+    if math.isnan(a) or math.isnan(b):
+        return math.isnan(a) and math.isnan(b)
+    if dtype == "f32":
+        return f32_bits(a) == f32_bits(b)
+    return a == b
+
+
+def check_moments(got: dict, want: dict, dtype: str = "f32", what: str = ""):
+    assert got["status"] == 0, (what, got)
+    assert got["count"] == want["count"], (what, got["count"], want["count"])
+    assert got["nan_count"] == want["nan_count"], (what, got["nan_count"], want["nan_count"])
+    if want["count"] == 0:
+        for k in ("mean", "m2", "std", "min", "max"):
+            assert math.isnan(got[k]), (what, k, got[k])
+        return
+    assert same_value(got["min"], want["min"], dtype), (what, "min", got["min"], want["min"])
+    assert same_value(got["max"], want["max"], dtype), (what, "max", got["max"], want["max"])
+    if not (math.isfinite(want["mean"]) and math.isfinite(want["std"])):
+        return  # infinities in the data: only NaN/inf-ness is compared
+    rms = math.hypot(want["mean"], want["std"])
+    assert abs(got["mean"] - want["mean"]) <= MEAN_REL * abs(want["mean"]) + MEAN_RMS * rms, \
+        (what, "mean", got["mean"], want["mean"])
+    if want["std"] == 0.0:
+        assert got["std"] == 0.0 and got["m2"] == 0.0, (what, got["std"])
+    else:
+        assert abs(got["std"] - want["std"]) <= STD_REL * want["std"], (what, "std", got["std"], want["std"])
+        assert abs(got["m2"] - want["m2"]) <= STD_REL * want["m2"] * 2, (what, "m2", got["m2"], want["m2"])
+
+
+def check_median(got_median: float, want_median: float, dtype: str = "f32", what: str = ""):
+    assert same_value(got_median, want_median, dtype), (what, "median", got_median, want_median)
+
+
+def as_u64(t) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint64) if hasattr(t, "cpu") else np.asarray(t).view(np.uint64)
+
+
+def check_hist(got_counts, got_outl, want_counts, want_outl, what: str = ""):
+    gc = as_u64(got_counts)
+    assert np.array_equal(gc, want_counts), (what, "counts differ at", np.nonzero(gc != want_counts)[0][:10])
+    if got_outl is not None:
+        assert np.array_equal(as_u64(got_outl), want_outl), (what, as_u64(got_outl), want_outl)

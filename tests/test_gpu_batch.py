@@ -1,0 +1,136 @@
+"""Batched region queries (one persistent kernel) against the CPU oracle, per query."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import check_hist, check_median, check_moments
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1211_4896_amd as tsa  # noqa: E402
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _boxes(dims, nq, seed, lo=1, hi=64):
+    r = synth.regions(nq, dims, seed, edge_lo=lo, edge_hi=hi)
+    nx, ny, nz = dims
+    extra = np.array([
+        [0, 0, 0, nx, ny, nz],          # whole cube
+        [3, 4, 5, 4, 5, 6],             # single voxel
+        [1, 0, 0, 4, ny, nz],           # narrow, unaligned
+        [0, 2, 2, nx, 3, 9],            # full rows
+        [nx - 5, ny - 1, nz - 1, nx, ny, nz],
+    ], dtype=np.int64)
+    return np.concatenate([r, extra])
+
+
+def _check_batch(host, dev, boxes, nbins, dtype="f32", tune=None, what=""):
+    res, hists = tsa.region_batch(dev, boxes, nbins, tune=tune)
+    hists = hists.cpu().numpy().view(np.uint64)
+    for i, b in enumerate(boxes):
+        r = {k: res[i][k].item() for k in res.dtype.names}
+        want = oracle.stats(host, nbins, tuple(int(v) for v in b))
+        tag = f"{what} q{i} {tuple(int(v) for v in b)}"
+        check_moments(r, want, dtype, tag)
+        check_median(r["median"], want["median"], dtype, tag)
+        assert bool(r["flags"] & tsa.FLAG_HIST_SKIPPED) == want["hist_skipped"], tag
+        if not want["hist_skipped"]:
+            check_hist(hists[i], None, want["counts"], None, tag)
+    return res, hists
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_batch_matches_oracle(seed):
+    spec = synth.scaled(synth.SPECS["c1"], 128, 96, 80)
+    spec = synth.CubeSpec(**{**spec.__dict__, "seed": 100 + seed})
+    host, _ = synth.generate(spec)
+    dev = _dev(host)
+    boxes = _boxes((128, 96, 80), 200, seed)
+    _say("case batch f32", seed, len(boxes))
+    _check_batch(host, dev, boxes, 64, what="f32")
+
+
+def test_batch_invalid_boxes_flagged():
+    host = np.random.default_rng(0).standard_normal((8, 9, 12)).astype(np.float32)
+    dev = _dev(host)
+    boxes = np.array([[0, 0, 0, 12, 9, 8], [0, 0, 0, 13, 1, 1], [2, 2, 2, 2, 3, 3], [-1, 0, 0, 1, 1, 1],
+                      [1, 1, 1, 5, 5, 5]], dtype=np.int64)
+    _say("case batch invalid boxes")
+    res, hists = tsa.region_batch(dev, boxes, 16)
+    for i in (1, 2, 3):
+        assert res[i]["status"] == tsa.TSA_EINVAL and res[i]["flags"] & tsa.FLAG_BAD_REGION
+    for i in (0, 4):
+        b = tuple(int(v) for v in boxes[i])
+        want = oracle.stats(host, 16, b)
+        check_moments({k: res[i][k].item() for k in res.dtype.names}, want, "f32", f"valid {b}")
+        check_median(res[i]["median"], want["median"], "f32", f"valid {b}")
+
+
+def test_batch_phase3_and_small_tiles():
+    """cand_max = 0 disables the candidate copy: every median takes the third
+    (data) pass.  Tiny tiles give many tiles per box."""
+    spec = synth.scaled(synth.SPECS["c1"], 96, 64, 48)
+    host, _ = synth.generate(spec)
+    dev = _dev(host)
+    boxes = _boxes((96, 64, 48), 60, 7, lo=2, hi=48)
+    _say("case batch phase3")
+    res, _ = _check_batch(host, dev, boxes, 32, tune=(1024, 256, 2, 0), what="phase3")
+    assert any(r["flags"] & tsa.FLAG_PHASE3 for r in res)
+    _say("case batch small tiles")
+    _check_batch(host, dev, boxes, 32, tune=(1024, 256, 8, 65536), what="small tiles")
+
+
+def test_batch_int16():
+    spec = synth.scaled(synth.SPECS["c5c"], 128, 64, 40)
+    host, _ = synth.generate(spec)
+    dev = _dev(host)
+    boxes = _boxes((128, 64, 40), 80, 3)
+    _say("case batch int16")
+    _check_batch(host, dev, boxes, 128, dtype="i16", what="i16")
+
+
+def test_batch_adversarial_cube():
+    rng = np.random.default_rng(11)
+    host = rng.integers(-2, 3, (16, 24, 40)).astype(np.float32)  # heavy ties
+    host[3:5] = np.nan  # NaN slab
+    host[10, :, :] = 7.0  # constant plane
+    host[12, 5, 5] = -0.0
+    dev = _dev(host)
+    boxes = np.array([[0, 0, 3, 40, 24, 5],      # all NaN
+                      [0, 0, 10, 40, 24, 11],    # constant
+                      [0, 0, 0, 40, 24, 16],     # everything
+                      [5, 5, 12, 6, 6, 13],      # a single -0
+                      [1, 2, 2, 39, 22, 14]], dtype=np.int64)
+    _say("case batch adversarial")
+    _check_batch(host, dev, boxes, 8, what="adv")
+
+
+def test_batch_deterministic_and_equal_to_single_calls():
+    spec = synth.scaled(synth.SPECS["c1"], 128, 128, 64)
+    host, _ = synth.generate(spec)
+    dev = _dev(host)
+    boxes = _boxes((128, 128, 64), 100, 5)
+    _say("case batch determinism")
+    r1, h1 = tsa.region_batch(dev, boxes, 256)
+    r2, h2 = tsa.region_batch(dev, boxes, 256)
+    assert r1.tobytes() == r2.tobytes() and torch.equal(h1, h2)
+    for i in range(0, len(boxes), 7):
+        b = tuple(int(v) for v in boxes[i])
+        one, c, _ = tsa.stats(dev, 256, b)
+        assert one["count"] == r1[i]["count"]
+        check_median(one["median"], r1[i]["median"], "f32", f"single {b}")
+        assert np.array_equal(c.cpu().numpy(), h1[i].cpu().numpy())
+        assert math.isclose(one["mean"], r1[i]["mean"], rel_tol=1e-12, abs_tol=1e-14)
