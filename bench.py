@@ -104,6 +104,8 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c1", "c2"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ops", action="store_true", help="skip the separate-call measurements")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run 3 plain 1 GiB device copies (reference dispatches for byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this path does not shard)",
@@ -191,9 +193,27 @@ def main():
 
     if not args.no_ops:
         line["ops"] = _separate_ops(tsa, api, dev, cp, N, float(res["min"]), float(res["max"]), nbins, sh)
+    if args.calib_copy:
+        line["calib_copy_bytes"] = _calib_copy(lib, dev.device, sh)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = _cpu_baseline(host, nbins)
     print(json.dumps(line), flush=True)
+
+
+def _calib_copy(lib, device, sh, nbytes: int = 1 << 30) -> int:
+    """Three plain copies of nbytes: their FETCH_SIZE / WRITE_SIZE per dispatch
+    calibrate the counters against a known byte count."""
+    import torch
+
+    lib.tsa_internal_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=device)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        st = lib.tsa_internal_copy(dst.data_ptr(), src.data_ptr(), nbytes, sh)
+        if st != 0:
+            raise RuntimeError(f"tsa_internal_copy failed ({st})")
+    torch.cuda.synchronize()
+    return nbytes
 
 
 def _separate_ops(tsa, api, dev, cp, N, lo, hi, nbins, sh, reps: int = 10) -> dict:

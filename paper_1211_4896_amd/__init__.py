@@ -27,7 +27,8 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libtsa.so")
+# TSA_LIB names another build of the same library (for timing one build against another)
+LIB_PATH = os.environ.get("TSA_LIB") or os.path.join(_HERE, "libtsa.so")
 
 TSA_OK, TSA_EINVAL, TSA_ENOMEM, TSA_EDEVICE, TSA_ENOTSUP, TSA_EBUSY = 0, -1, -2, -3, -4, -5
 TSA_F32, TSA_I16 = 0, 1

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtsa.so")
 
-SOURCES = ["tsa_kernels.hip", "tsa_hist_wide.hip", "tsa_batch.hip", "tsa_trace.hip", "tsa_api.hip"]
+SOURCES = ["tsa_kernels.hip", "tsa_hist_wide.hip", "tsa_batch.hip", "tsa_serve.hip", "tsa_trace.hip", "tsa_api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -28,10 +28,12 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(out: str = LIB, verbose: bool = False) -> str:
+def build(out: str = LIB, verbose: bool = False, extra_flags=()) -> str:
+    """Compile every source into one shared library (extra_flags: e.g. -D
+    switches of kernel variants, for timing one build against another)."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = out + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-o", tmp,
+    cmd = [hipcc, *HIPCC_FLAGS, *extra_flags, "-I", os.path.join(ROOT, "include"), "-o", tmp,
            *[os.path.join(CSRC, s) for s in SOURCES]]
     if verbose:
         print(" ".join(cmd), file=sys.stderr)

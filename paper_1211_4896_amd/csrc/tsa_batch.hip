@@ -418,7 +418,10 @@ TSA_DEV void epilogue1(const BArgs& a, uint32_t q, BShared& sh) {
         s.scale = scale;
         s.hist_ok = ok;
         if (!ok) R.flags |= TSA_FLAG_HIST_SKIPPED;
-        s.var_on = (DT == 0 && isfinite(mean)) ? 1u : 0u;
+        s.var_on = (DT == 0 && isfinite(mean) &&
+                    one_pass_m2_at_risk(mean, R.m2 / (double)cnt, fmax(fabs((double)lo), fabs((double)hi))))
+                       ? 1u
+                       : 0u;
         s.shift = s.var_on ? (float)mean : 0.0f;
         s.vscale = s.var_on ? var_scale_exp(fmax(fabs((double)hi - (double)s.shift), fabs((double)lo - (double)s.shift)))
                             : 0;
@@ -572,7 +575,7 @@ struct BPass2 {
       if (var_on) var(raw, in);
     }
   }
-  TSA_DEV void chunk() {}
+  TSA_DEV void chunk() { l2.chunk(); }
 };
 
 template <int DT, bool VEC, bool NT, class F>
@@ -592,6 +595,7 @@ template <int DT, bool VEC, bool NT>
 __global__ __launch_bounds__(kBBlock) void k_batch(BArgs a) {
   extern __shared__ uint32_t lds[];
   __shared__ BShared sh;
+  __shared__ CandShared cs;
   const int t = threadIdx.x;
   const uint64_t T1 = a.hdr->T1;
   for (;;) {
@@ -633,7 +637,7 @@ __global__ __launch_bounds__(kBBlock) void k_batch(BArgs a) {
     QState& s = a.st[q];
 
     if (phase == 1) {
-      lds_zero(lds, kBins1);
+      lds_zero(lds, kBins1 + kTrash);
       __syncthreads();
       BPass1<DT> f{MomAcc<DT>{}, Digit1Acc<DT>{lds, 0u, 0u}};
       walk_tile<DT, VEC, NT>(a, g, tile, f);
@@ -647,16 +651,18 @@ __global__ __launch_bounds__(kBBlock) void k_batch(BArgs a) {
     } else if (phase == 2) {
       if (!block_wait_ge(&s.p1_ready, 1u, &a.hdr->err, sh)) return;
       if (!s.skip2) {
-        const uint32_t hsize = (uint32_t)a.nbins << a.rshift;
+        const uint32_t hsize = ((uint32_t)a.nbins << a.rshift) + kTrash;
         uint32_t* l2 = lds + hsize;
         lds_zero(lds, hsize + kBins2);
+        cand_init(cs);
         __syncthreads();
         const bool hist_on = s.hist_ok != 0, var_on = DT == 0 && s.var_on != 0;
         BPass2<DT> f{HistAcc{lds, s.lo, s.hi, s.scale, a.nbins - 1, a.rshift, (uint32_t)t & ((1u << a.rshift) - 1u)},
-                     Level2Acc<DT>{l2, s.prefix >> kShift1, s.compact != 0, a.pool + s.cand_base, &s.cand_fill,
-                                   s.cand_n},
+                     Level2Acc<DT>{l2, s.prefix >> kShift1, s.compact != 0,
+                                   CandSink{&cs, a.pool + s.cand_base, &s.cand_fill, s.cand_n}},
                      VarAcc{s.shift, s.vscale}, hist_on, var_on};
         walk_tile<DT, VEC, NT>(a, g, tile, f);
+        f.l2.finish();
         __syncthreads();
         if (hist_on) lds_flush(lds, (uint32_t)a.nbins, a.rshift, a.hists + (size_t)q * a.nbins);
         uint32_t* dig = a.digits + (size_t)q * kBins1;
@@ -827,8 +833,8 @@ int run_region_batch(const tsa_cube* cube, const tsa_region* d_regions, int32_t 
   a.digits = (uint32_t*)(ws + L.digits);
   a.pool = (uint32_t*)(ws + L.pool);
   hipStream_t s = (hipStream_t)stream;
-  const size_t lds1 = (size_t)kBins1 * 4;
-  const size_t lds2 = (((size_t)nbins << a.rshift) + kBins2) * 4;
+  const size_t lds1 = ((size_t)kBins1 + kTrash) * 4;
+  const size_t lds2 = (((size_t)nbins << a.rshift) + kTrash + kBins2) * 4;
   const size_t lds = lds1 > lds2 ? lds1 : lds2;
   bfill(a.hdr, sizeof(BatchHdr) / 4, s);
   bfill(a.digits, (size_t)kBins1 * nq, s);

@@ -18,6 +18,13 @@ constexpr int kWave = 64;
 constexpr int kShift1 = 20, kShift2 = 8;
 constexpr int kBins1 = 4096, kBins2 = 4096, kBins3 = 256;
 
+// Whether the one-pass M2 = Q - S^2/n (float-float Q and S) can miss the
+// stated accuracy: cancellation when mean^2 > 9 var (the error grows with
+// 1 + mean^2/var), or single-precision squares near overflow or underflow.
+TSA_DEV bool one_pass_m2_at_risk(double mean, double var1, double amax) {
+  return !(var1 > 0.0) || mean * mean > 9.0 * var1 || amax > 0x1p50 || amax < 0x1p-50;
+}
+
 // Exponent s with 2^s * dev near 2^40: squares of scaled deviations stay far
 // from float overflow and underflow for any finite extent dev > 0.
 TSA_DEV int32_t var_scale_exp(double dev) {

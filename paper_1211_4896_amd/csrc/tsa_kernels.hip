@@ -34,7 +34,7 @@ __global__ __launch_bounds__(1024) void k_hist(Geom g, float lo, float hi, float
                                                uint64_t* __restrict__ outl) {
   extern __shared__ uint32_t lds[];
   __shared__ uint32_t osm[32];
-  lds_zero(lds, (uint32_t)nbins << rshift);
+  lds_zero(lds, ((uint32_t)nbins << rshift) + kTrash);
   __syncthreads();
   HistAcc h{lds, lo, hi, scale, nbins - 1, rshift, threadIdx.x & ((1u << rshift) - 1u)};
   walk<DT, VEC, kUnroll, NT>(g, h);
@@ -49,7 +49,7 @@ __global__ __launch_bounds__(1024) void k_hist(Geom g, float lo, float hi, float
 template <int DT, bool VEC, bool NT>
 __global__ __launch_bounds__(1024) void k_level1(Geom g, uint32_t rshift, uint64_t* __restrict__ hist1) {
   extern __shared__ uint32_t lds[];
-  lds_zero(lds, (uint32_t)kBins1 << rshift);
+  lds_zero(lds, ((uint32_t)kBins1 << rshift) + kTrash);
   __syncthreads();
   Digit1Acc<DT> d{lds, rshift, threadIdx.x & ((1u << rshift) - 1u)};
   walk<DT, VEC, kUnroll, NT>(g, d);
@@ -61,11 +61,14 @@ template <int DT, bool VEC, bool NT>
 __global__ __launch_bounds__(1024) void k_level2(Geom g, SelState* __restrict__ st, uint64_t* __restrict__ hist2,
                                                  uint32_t* __restrict__ cand) {
   __shared__ uint32_t lds[kBins2];
+  __shared__ CandShared cs;
   if (st->done) return;
   lds_zero(lds, kBins2);
+  cand_init(cs);
   __syncthreads();
-  Level2Acc<DT> a{lds, st->prefix >> kShift1, st->compact != 0, cand, &st->ncand, st->cand_cap};
+  Level2Acc<DT> a{lds, st->prefix >> kShift1, st->compact != 0, CandSink{&cs, cand, &st->ncand, st->cand_cap}};
   walk<DT, VEC, kUnroll, NT>(g, a);
+  a.finish();
   __syncthreads();
   lds_flush(lds, kBins2, 0, hist2);
 }
@@ -339,7 +342,7 @@ __global__ __launch_bounds__(1024) void k_pass_a(Geom g, uint32_t rshift, Partia
                                                  uint64_t* __restrict__ hist1) {
   extern __shared__ uint32_t lds[];
   __shared__ MomShared sm;
-  lds_zero(lds, (uint32_t)kBins1 << rshift);
+  lds_zero(lds, ((uint32_t)kBins1 << rshift) + kTrash);
   __syncthreads();
   PassA<DT> a{MomAcc<DT>{}, Digit1Acc<DT>{lds, rshift, threadIdx.x & ((1u << rshift) - 1u)}};
   walk<DT, VEC, kUnroll, NT>(g, a);
@@ -380,7 +383,9 @@ __global__ __launch_bounds__(1024) void k_mid(const Partial* __restrict__ parts,
     st->scale = scale;
     // pass B recomputes M2 about c = fl32(mean) when the values differ (float32 cubes)
     const double mean = out->mean;
-    const bool von = dtype == 0 && n > 0 && kmin != kmax && isfinite(mean);
+    const double amax = fmax(fabs((double)lo), fabs((double)hi));
+    const bool von = dtype == 0 && n > 0 && kmin != kmax && isfinite(mean) &&
+                     one_pass_m2_at_risk(mean, out->m2 / (double)n, amax);
     st->shift = von ? (float)mean : 0.0f;
     st->var_on = von ? 1u : 0u;
     st->vscale = von ? var_scale_exp(fmax(fabs((double)hi - (double)(float)mean), fabs((double)lo - (double)(float)mean)))
@@ -406,7 +411,7 @@ struct PassB {
       if (var_on) var(raw, in);
     }
   }
-  TSA_DEV void chunk() {}
+  TSA_DEV void chunk() { l2.chunk(); }
 };
 
 template <int DT, bool VEC, bool NT>
@@ -417,19 +422,22 @@ __global__ __launch_bounds__(1024) void k_pass_b(Geom g, int32_t nbins, uint32_t
   extern __shared__ uint32_t lds[];  // [nbins << rshift] histogram, then [kBins2] level-2 digits
   __shared__ uint32_t osm[32];
   __shared__ MomShared sm;
-  const uint32_t hsize = (uint32_t)nbins << rshift;
+  __shared__ CandShared cs;
+  const uint32_t hsize = ((uint32_t)nbins << rshift) + kTrash;
   uint32_t* l2 = lds + hsize;
   const bool hist_on = st->hist_ok != 0;
   const bool sel_on = st->done == 0;
   const bool var_on = DT == 0 && st->var_on != 0;
   if (!hist_on && !sel_on && !var_on) return;
   lds_zero(lds, hsize + kBins2);
+  cand_init(cs);
   __syncthreads();
   PassB<DT> b{HistAcc{lds, st->lo, st->hi, st->scale, nbins - 1, rshift, threadIdx.x & ((1u << rshift) - 1u)},
-              Level2Acc<DT>{l2, sel_on ? (st->prefix >> kShift1) : 0xFFFFFFFFu, sel_on && st->compact != 0, cand,
-                            &st->ncand, st->cand_cap},
+              Level2Acc<DT>{l2, sel_on ? (st->prefix >> kShift1) : 0xFFFFFFFFu, sel_on && st->compact != 0,
+                            CandSink{&cs, cand, &st->ncand, st->cand_cap}},
               VarAcc{st->shift, st->vscale}, hist_on, var_on};
   walk<DT, VEC, kUnroll, NT>(g, b);
+  b.l2.finish();
   __syncthreads();
   if (hist_on) lds_flush(lds, (uint32_t)nbins, rshift, counts);
   if (sel_on) lds_flush(l2, kBins2, 0, hist2);
@@ -776,7 +784,7 @@ int run_histogram(const tsa_cube* cube, const tsa_region* region, float lo, floa
   fill32(outl, 4, 0u, P.s);
   const size_t budget = P.dev.lds_per_block < 65536 ? P.dev.lds_per_block : 65536;
   const uint32_t rs = rep_shift_for(nbins, budget);
-  const size_t lds = ((size_t)nbins << rs) * 4;
+  const size_t lds = (((size_t)nbins << rs) + kTrash) * 4;
   if (lds <= budget) {
     TSA_TRACED("hist", P.s,
     TSA_DISPATCH(cube->dtype, P.vec, tuning().nt,
@@ -819,7 +827,7 @@ int run_median(const tsa_cube* cube, const tsa_region* region, tsa_result* d_out
   const uint32_t rs = rep_shift_for(kBins1, 32768);
   TSA_TRACED("level1", P.s,
     TSA_DISPATCH(cube->dtype, P.vec, tuning().nt,
-                 hipLaunchKernelGGL((k_level1<DT, VEC, NT>), dim3(P.grid), dim3(P.block), ((size_t)kBins1 << rs) * 4,
+                 hipLaunchKernelGGL((k_level1<DT, VEC, NT>), dim3(P.grid), dim3(P.block), (((size_t)kBins1 << rs) + kTrash) * 4,
                                     P.s, P.g, rs, h1)));
   TSA_TRACED("select", P.s,
              hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, P.s, 1, (const uint64_t*)h1, stp, cube->dtype,
@@ -838,7 +846,7 @@ int run_stats(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa
   int st = prepare(cube, region, d_ws, ws_bytes, stream, &P);
   if (st) return st;
   const size_t budget = P.dev.lds_per_block < 65536 ? P.dev.lds_per_block : 65536;
-  if ((size_t)nbins * 4 + kBins2 * 4 > budget) return TSA_ENOTSUP;
+  if (((size_t)nbins + kTrash + kBins2) * 4 > budget) return TSA_ENOTSUP;
   reset_select(P);
   uint64_t* outl = d_outliers ? d_outliers : (uint64_t*)(P.ws + P.L.outl);
   fill32(d_counts, (size_t)nbins * 2, 0u, P.s);
@@ -851,13 +859,13 @@ int run_stats(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa
   const uint32_t rs1 = rep_shift_for(kBins1, 32768);
   TSA_TRACED("pass_a", P.s,
     TSA_DISPATCH(cube->dtype, P.vec, tuning().nt,
-                 hipLaunchKernelGGL((k_pass_a<DT, VEC, NT>), dim3(P.grid), dim3(P.block), ((size_t)kBins1 << rs1) * 4,
+                 hipLaunchKernelGGL((k_pass_a<DT, VEC, NT>), dim3(P.grid), dim3(P.block), (((size_t)kBins1 << rs1) + kTrash) * 4,
                                     P.s, P.g, rs1, parts, h1)));
   TSA_TRACED("mid", P.s,
              hipLaunchKernelGGL(k_mid, dim3(1), dim3(1024), 0, P.s, (const Partial*)parts, P.grid, cube->dtype,
                                 (uint64_t)P.volume, nbins, (const uint64_t*)h1, stp, d_out));
-  uint32_t rsb = rep_shift_for(nbins, budget - kBins2 * 4);
-  const size_t ldsb = ((size_t)nbins << rsb) * 4 + kBins2 * 4;
+  uint32_t rsb = rep_shift_for(nbins, budget - (kBins2 + kTrash) * 4);
+  const size_t ldsb = (((size_t)nbins << rsb) + kTrash + kBins2) * 4;
   Partial* parts2 = (Partial*)(P.ws + P.L.partials2);
   TSA_TRACED("pass_b", P.s,
     TSA_DISPATCH(cube->dtype, P.vec, tuning().nt,

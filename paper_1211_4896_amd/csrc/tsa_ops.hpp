@@ -5,6 +5,13 @@
 
 #include "tsa_device.hpp"
 
+#ifndef TSA_BRANCHLESS
+#define TSA_BRANCHLESS 0
+#endif
+#ifndef TSA_BALLOT_COUNT
+#define TSA_BALLOT_COUNT 0
+#endif
+
 namespace tsa {
 
 // ---- validity and key of one element ---------------------------------------
@@ -50,7 +57,11 @@ struct MomAcc<0> {
     const uint32_t k = Elt<0>::key(x);
     kmin = min(kmin, ok ? k : 0xFFFFFFFFu);
     kmax = max(kmax, ok ? k : 0u);
+#if TSA_BALLOT_COUNT
+    cnt += (uint32_t)__popcll(__ballot(ok));  // wave total, kept uniform (scalar unit)
+#else
     cnt += ok ? 1u : 0u;
+#endif
   }
   TSA_DEV void chunk() {}
 };
@@ -98,7 +109,11 @@ TSA_DEV void block_store_partial(MomAcc<0>& a, MomShared& sm, Partial* out) {
     dw_add(a.qh, a.ql, bqh, bql);
   }
   const uint32_t kmin = wave_min_u32(a.kmin), kmax = wave_max_u32(a.kmax);
+#if TSA_BALLOT_COUNT
+  const uint64_t cnt = a.cnt;  // already the wave's total
+#else
   const uint64_t cnt = wave_sum_u64(a.cnt);
+#endif
   const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   if (lane == 0) {
     sm.sh[w] = a.sh;
@@ -228,6 +243,10 @@ TSA_DEV void block_store_var(VarAcc& a, MomShared& sm, Partial* out) {
 }
 
 // ---- LDS-privatised counters -------------------------------------------------
+// Every LDS counter array is followed by kTrash spare words (one per lane of a
+// wave) that branch-free increments of invalid lanes may hit; they are never read.
+constexpr uint32_t kTrash = 64;
+
 // Bin b, replica r lives at lds[(b << rshift) + r]; a lane uses replica
 // (lane & (R-1)) so lanes of one wave that hit the same bin mostly touch
 // different words.
@@ -261,12 +280,22 @@ struct HistAcc {
     const float v = (float)raw;  // exact for int16
     below += (in && v < lo) ? 1u : 0u;
     above += (in && v > hi) ? 1u : 0u;
+#if TSA_BRANCHLESS
+    const float d = v - lo;
+    const float t = d * scale;  // lo == hi: scale == 0 and t == 0
+    const int32_t b = min(max((int32_t)t, 0), nbm1);
+    // out-of-range and NaN lanes count into spare words past the bins
+    const uint32_t idx = (in && v >= lo && v <= hi) ? ((uint32_t)b << rshift) + rep
+                                                    : ((uint32_t)(nbm1 + 1) << rshift) + (threadIdx.x & 63u);
+    lds_inc(lds, idx);
+#else
     if (in && v >= lo && v <= hi) {  // NaN fails both tests
       const float d = v - lo;
       const float t = d * scale;  // lo == hi: scale == 0 and t == 0
       const int32_t b = min(max((int32_t)t, 0), nbm1);
       lds_inc(lds, ((uint32_t)b << rshift) + rep);
     }
+#endif
   }
   TSA_DEV void chunk() {}
 };
@@ -298,22 +327,86 @@ struct Digit1Acc {  // top 12 key bits of every valid element
   uint32_t rshift, rep;
   template <class T>
   TSA_DEV void operator()(T raw, bool in) {
+#if TSA_BRANCHLESS
+    // invalid lanes count into spare words past the bins (one per lane)
+    const uint32_t idx = Elt<DT>::valid(raw, in) ? ((Elt<DT>::key(raw) >> kShift1) << rshift) + rep
+                                                   : ((uint32_t)kBins1 << rshift) + (threadIdx.x & 63u);
+    lds_inc(lds, idx);
+#else
     if (Elt<DT>::valid(raw, in)) lds_inc(lds, ((Elt<DT>::key(raw) >> kShift1) << rshift) + rep);
+#endif
   }
   TSA_DEV void chunk() {}
 };
 
-// Append the lanes' keys whose flag is set to a global list (one atomic per wave).
-TSA_DEV void wave_append(bool m, uint32_t key, uint32_t* list, uint32_t* counter, uint32_t cap) {
+// Candidate keys are staged per block in LDS and copied to the global list in
+// runs, so the global counter sees one atomic per run instead of one per wave.
+constexpr uint32_t kCandStage = 2048;  // staged keys per block
+
+struct CandShared {
+  uint32_t buf[kCandStage];
+  uint32_t cnt;        // keys claimed in buf (may exceed kCandStage)
+  uint32_t valid_end;  // buf[0, valid_end) is filled when cnt > kCandStage
+  uint32_t gbase;
+};
+
+TSA_DEV void cand_init(CandShared& cs) {
+  if (threadIdx.x == 0) {
+    cs.cnt = 0;
+    cs.valid_end = kCandStage;
+  }
+}
+
+struct CandSink {
+  CandShared* cs;
+  uint32_t* list;     // global list
+  uint32_t* counter;  // global fill counter
+  uint32_t cap;       // global capacity
+};
+
+// Wave-aggregated append: one LDS atomic per wave; a wave that does not fit
+// in the stage writes straight to the global list.
+TSA_DEV void cand_append(bool m, uint32_t key, const CandSink& k) {
   const uint64_t bal = __ballot(m);
   if (bal == 0) return;
   const int lane = threadIdx.x % kWave;
   const int leader = __ffsll((unsigned long long)bal) - 1;
-  uint32_t base = 0;
-  if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(bal));
-  base = __shfl(base, leader);
+  const uint32_t n = (uint32_t)__popcll(bal);
+  uint32_t pos = 0;
+  if (lane == leader) {
+    pos = __hip_atomic_fetch_add(&k.cs->cnt, n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (pos <= kCandStage && pos + n > kCandStage) k.cs->valid_end = pos;  // the one wave that crosses the end
+  }
+  pos = __shfl(pos, leader);
   const uint32_t off = (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
-  if (m && base + off < cap) list[base + off] = key;
+  if (pos + n <= kCandStage) {
+    if (m) k.cs->buf[pos + off] = key;
+  } else {
+    uint32_t g = 0;
+    if (lane == leader) g = atomicAdd(k.counter, n);
+    g = __shfl(g, leader);
+    if (m && g + off < k.cap) k.list[g + off] = key;
+  }
+}
+
+// Whole block: copy the staged keys out when at least `threshold` are staged.
+TSA_DEV void cand_flush(const CandSink& k, uint32_t threshold) {
+  __syncthreads();
+  const uint32_t c = k.cs->cnt;
+  const uint32_t nvalid = c <= kCandStage ? c : k.cs->valid_end;
+  __syncthreads();  // every thread has read the count before any thread appends again
+  if (c == 0 || c < threshold) return;  // uniform: every thread read the same count
+  if (threadIdx.x == 0) k.cs->gbase = nvalid ? atomicAdd(k.counter, nvalid) : 0u;
+  __syncthreads();
+  const uint32_t g = k.cs->gbase;
+  for (uint32_t i = threadIdx.x; i < nvalid; i += blockDim.x)
+    if (g + i < k.cap) k.list[g + i] = k.cs->buf[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    k.cs->cnt = 0;
+    k.cs->valid_end = kCandStage;
+  }
+  __syncthreads();
 }
 
 template <int DT>
@@ -321,17 +414,20 @@ struct Level2Acc {  // keys inside the level-1 bucket: next 12 bits, optional co
   uint32_t* lds;
   uint32_t p1;
   bool compact;
-  uint32_t* cand;
-  uint32_t* ncand;
-  uint32_t cap;
+  CandSink sink;
   template <class T>
   TSA_DEV void operator()(T raw, bool in) {
     const uint32_t key = Elt<DT>::key(raw);
     const bool m = Elt<DT>::valid(raw, in) && (key >> kShift1) == p1;
     if (m) lds_inc(lds, (key >> kShift2) & 0xFFFu);
-    if (compact) wave_append(m, key, cand, ncand, cap);
+    if (compact) cand_append(m, key, sink);
   }
-  TSA_DEV void chunk() {}
+  TSA_DEV void chunk() {
+    if (compact) cand_flush(sink, kCandStage / 2);
+  }
+  TSA_DEV void finish() {
+    if (compact) cand_flush(sink, 1);
+  }
 };
 
 template <int DT>

@@ -89,3 +89,25 @@ def test_null_pointers_rejected():
     assert c.tsa_histogram(ctypes.byref(cube), None, 0.0, 1.0, 8, None, None, 0x20000, 1 << 30, None) == tsa.TSA_EINVAL
     assert c.tsa_moments(None, None, 0x30000, 0x20000, 1 << 30, None) == tsa.TSA_EINVAL
     assert c.tsa_stats(ctypes.byref(cube), None, 0, 0x30000, 0x40000, None, 0x20000, 1 << 30, None) == tsa.TSA_EINVAL
+
+
+def test_server_config_rejected_before_device():
+    from paper_1211_4896_amd import serve
+    lib = serve._bind()
+    h = ctypes.c_void_p()
+    for bad in [serve.ServerConfig(0, 1, 1, 8, 8, 0, 0), serve.ServerConfig(8, 0, 1, 8, 8, 0, 0),
+                serve.ServerConfig(8, 5, 1, 8, 8, 0, 0), serve.ServerConfig(8, 1, 0, 8, 8, 0, 0),
+                serve.ServerConfig(8, 1, 1, 5000, 8, 0, 0), serve.ServerConfig(8, 1, 1, 8, 70000, 0, 0),
+                serve.ServerConfig(8, 1, 1, 8, 8, 1, 0)]:
+        assert lib.tsa_server_create(ctypes.byref(bad), ctypes.byref(h)) == tsa.TSA_EINVAL
+    assert lib.tsa_server_now() > 0
+
+
+def test_batch_workspace_bytes():
+    c = tsa.capi()
+    cube = _cube(64, 64, 64)
+    n1 = c.tsa_workspace_bytes(tsa.OP_REGION_BATCH, ctypes.byref(cube), None, 256, 1)
+    n2 = c.tsa_workspace_bytes(tsa.OP_REGION_BATCH, ctypes.byref(cube), None, 256, 4096)
+    assert 0 < n1 < n2
+    assert c.tsa_workspace_bytes(tsa.OP_REGION_BATCH, ctypes.byref(cube), None, 4097, 8) == 0
+    assert c.tsa_workspace_bytes(tsa.OP_REGION_BATCH, ctypes.byref(cube), None, 256, 65537) == 0
