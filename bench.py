@@ -106,6 +106,11 @@ def main():
     ap.add_argument("--no-ops", action="store_true", help="skip the separate-call measurements")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run 3 plain 1 GiB device copies (reference dispatches for byte counters)")
+    ap.add_argument("--no-region", action="store_true", help="skip the batched-vs-plain region queries (c4)")
+    ap.add_argument("--region-reps", type=int, default=5)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving run (c5)")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-qps", type=float, default=2000.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this path does not shard)",
@@ -195,9 +200,163 @@ def main():
         line["ops"] = _separate_ops(tsa, api, dev, cp, N, float(res["min"]), float(res["max"]), nbins, sh)
     if args.calib_copy:
         line["calib_copy_bytes"] = _calib_copy(lib, dev.device, sh)
+    del dev, ws
+    torch.cuda.empty_cache()
+    if not args.no_region:
+        line["region_batch"] = _region_batch_bench(tsa, torch, np, synth, args.region_reps)
+        torch.cuda.empty_cache()
+    if not args.no_serve:
+        line["serving"] = _serving_bench(torch, np, synth, args.serve_seconds, args.serve_qps)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = _cpu_baseline(host, nbins)
     print(json.dumps(line), flush=True)
+
+
+def _region_batch_bench(tsa, torch, np, synth, reps: int) -> dict:
+    """c4: 4096 boxes (edges log-uniform [8,512]) on a resident 2048^3 float32
+    cube, each getting moments + 256-bin histogram over its own [min,max] +
+    median.  Batched = one tsa_region_batch call (one persistent launch).
+    Plain = the same library per box: tsa_moments, host sync and read of
+    min/max, tsa_histogram, tsa_median, host sync."""
+    spec = synth.SPECS["c4"]
+    t0 = time.perf_counter()
+    host, _ = synth.generate(spec)
+    t_gen = time.perf_counter() - t0
+    dev = torch.from_numpy(host).to("cuda:0")
+    del host
+    torch.cuda.synchronize()
+    nq, nbins = 4096, 256
+    boxes = synth.regions(nq, (spec.nx, spec.ny, spec.nz), seed=2024, edge_lo=8, edge_hi=512)
+    vox = int(np.prod(boxes[:, 3:] - boxes[:, :3], axis=1).sum())
+    d_boxes = torch.from_numpy(boxes).to(dev.device)
+    ws = tsa.workspace(tsa.OP_REGION_BATCH, dev, None, nbins, nq)
+    res_buf = torch.empty(72 * nq, dtype=torch.uint8, device=dev.device)
+    hists = torch.empty((nq, nbins), dtype=torch.int64, device=dev.device)
+    api = tsa.capi()
+    c = tsa.cube_of(dev)
+    sh = torch.cuda.current_stream().cuda_stream
+
+    def batch():
+        st = api.tsa_region_batch(ctypes.byref(c), d_boxes.data_ptr(), nq, nbins, res_buf.data_ptr(),
+                                  hists.data_ptr(), None, ws.data_ptr(), ws.numel(), sh)
+        if st != 0:
+            raise RuntimeError(f"tsa_region_batch: {tsa.status_string(st)}")
+
+    batch()
+    torch.cuda.synchronize()
+    lib = api.lib
+    _trace(lib, True, cap=reps * 16)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        batch()
+    e1.record()
+    torch.cuda.synchronize()
+    kern = _trace_read(lib)
+    _trace(lib, False)
+    b_ms = e0.elapsed_time(e1) / reps
+    res = tsa.results_to_numpy(res_buf)
+    bad = int(np.count_nonzero(res["status"] != 0))
+    phase3 = int(np.count_nonzero(res["flags"] & tsa.FLAG_PHASE3))
+
+    # plain per-query path over the same boxes
+    ws1 = torch.empty(max(api.tsa_workspace_bytes(op, ctypes.byref(c), None, nbins, 0) for op in (0, 1, 2)),
+                      dtype=torch.uint8, device=dev.device)
+    out = torch.empty(72, dtype=torch.uint8, device=dev.device)
+    counts = torch.empty(nbins, dtype=torch.int64, device=dev.device)
+    outl = torch.empty(2, dtype=torch.int64, device=dev.device)
+    host_out = torch.empty(72, dtype=torch.uint8, pin_memory=True)
+
+    def plain(b):
+        reg = tsa.Region(*(int(v) for v in b))
+        rp = ctypes.byref(reg)
+        api.tsa_moments(ctypes.byref(c), rp, out.data_ptr(), ws1.data_ptr(), ws1.numel(), sh)
+        host_out.copy_(out)  # synchronous: min/max needed on the host
+        r = host_out.numpy().view(tsa.RESULT_DTYPE)[0]
+        if r["count"] > 0 and np.isfinite(r["min"]) and np.isfinite(r["max"]):
+            api.tsa_histogram(ctypes.byref(c), rp, float(r["min"]), float(r["max"]), nbins, counts.data_ptr(),
+                              outl.data_ptr(), ws1.data_ptr(), ws1.numel(), sh)
+        api.tsa_median(ctypes.byref(c), rp, out.data_ptr(), ws1.data_ptr(), ws1.numel(), sh)
+        host_out.copy_(out)
+
+    for b in boxes[:16]:
+        plain(b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b in boxes:
+        plain(b)
+    torch.cuda.synchronize()
+    p_s = time.perf_counter() - t0
+    batched_qps = nq / (b_ms * 1e-3)
+    plain_qps = nq / p_s
+    kb = kern.get("batch", [1, b_ms, 0, 0])
+    batch_kernel_ms = kb[1] / kb[0]
+    return {"workload": "c4: 2048^3 float32 cube (noise + sources + 0.5% NaN), 4096 boxes, edges round(exp U[ln 8, "
+                        "ln 512]) per axis; moments + 256-bin histogram over own [min,max] + exact median each",
+            "queries": nq, "voxels_per_batch": vox, "batched_ms": round(b_ms, 3),
+            "batched_qps": round(batched_qps, 1), "plain_qps": round(plain_qps, 1),
+            "ratio": round(batched_qps / plain_qps, 2),
+            "batched_gvoxel_s": round(vox / (b_ms * 1e-3) / 1e9, 1),
+            "persistent_kernel_ms": round(batch_kernel_ms, 3),
+            "hbm_frac_2_passes": round(2 * 4.0 * vox / (batch_kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "kernels_ms": {k: round(v[1] / v[0], 4) for k, v in kern.items()},
+            "status_errors": bad, "phase3_queries": phase3, "generate_s": round(t_gen, 1)}
+
+
+def _serving_bench(torch, np, synth, seconds: float, qps: float) -> dict:
+    """c5: open-loop Poisson arrivals over three resident cubes (float32 1024^3,
+    float32 2048x2048x1024, int16 2048^3): 90% region requests (c4 boxes), 10%
+    full-cube requests (half 4096-bin histograms over the cube's [min,max],
+    half medians).  Latency = completion - submission."""
+    from paper_1211_4896_amd import serve
+
+    names = ["c5a", "c5b", "c5c"]
+    devs = []
+    for nm in names:
+        host, _ = synth.generate(synth.SPECS[nm])
+        devs.append(torch.from_numpy(host).to("cuda:0"))
+        del host
+    torch.cuda.synchronize()
+    warm = 2.0
+    n = int((warm + seconds) * qps)
+    rng = np.random.default_rng(77)
+    t_arr = serve.poisson_arrivals(qps, n, seed=78)
+    srv = serve.Server(max_batch=1024, region_lanes=2, max_admitted=8192, region_nbins=256, full_nbins=4096)
+    try:
+        ids = [srv.add_cube(d) for d in devs]
+        reqs = []
+        for i in range(n):
+            ci = int(rng.integers(0, 3))
+            spec = synth.SPECS[names[ci]]
+            if rng.random() < 0.1:
+                kind = serve.REQ_FULL_HIST if rng.random() < 0.5 else serve.REQ_FULL_MEDIAN
+                reqs.append(srv.request(ids[ci], kind, None, None, tag=i))
+            else:
+                b = synth.regions(1, (spec.nx, spec.ny, spec.nz), seed=1000003 + i, edge_lo=8, edge_hi=512)[0]
+                reqs.append(srv.request(ids[ci], serve.REQ_REGION, b, None, tag=i))
+        out = srv.replay(reqs, t_arr)
+        st = srv.stats()
+    finally:
+        srv.close()
+    keep = [o for o, t in zip(out, t_arr) if t >= warm]
+    lat = np.array([o.t_done - o.t_submit for o in keep]) * 1e3
+    kinds = np.array([o.kind for o in keep])
+    t_first = min(o.t_submit for o in keep)
+    t_last = max(o.t_done for o in keep)
+    errs = sum(1 for o in out if o.status != 0)
+
+    def pct(x, q):
+        return round(float(np.percentile(x, q)), 3) if x.size else None
+
+    return {"workload": "c5: float32 1024^3 + float32 2048x2048x1024 + int16 2048^3 resident; Poisson arrivals; 90% "
+                        "region (c4 boxes, 256 bins), 5% full-cube 4096-bin histogram, 5% full-cube median",
+            "offered_qps": qps, "measured_s": seconds, "warmup_s": warm, "requests": len(keep),
+            "achieved_qps": round(len(keep) / (t_last - t_first), 1),
+            "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "p999_ms": pct(lat, 99.9),
+            "p50_region_ms": pct(lat[kinds == 0], 50), "p99_region_ms": pct(lat[kinds == 0], 99),
+            "p50_full_ms": pct(lat[kinds != 0], 50), "p99_full_ms": pct(lat[kinds != 0], 99),
+            "errors": errs, "scheduler": st}
 
 
 def _calib_copy(lib, device, sh, nbytes: int = 1 << 30) -> int:

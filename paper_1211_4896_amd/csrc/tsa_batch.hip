@@ -18,6 +18,9 @@
 // boxes left unfinished report TSA_EDEVICE.
 #include <math.h>
 
+#include <mutex>
+#include <vector>
+
 #include "tsa_internal.hpp"
 
 namespace tsa {
@@ -575,7 +578,7 @@ struct BPass2 {
       if (var_on) var(raw, in);
     }
   }
-  TSA_DEV void chunk() { l2.chunk(); }
+  TSA_DEV void chunk() {}
 };
 
 template <int DT, bool VEC, bool NT, class F>
@@ -784,9 +787,118 @@ size_t batch_ws_bytes(const tsa_cube* cube, int32_t nbins, int32_t nq) {
 
 static void bfill(void* p, size_t words, hipStream_t s);
 
+static int enqueue_region_batch(const tsa_cube* cube, const tsa_region* d_regions, int32_t nq, int32_t nbins,
+                                tsa_result* d_results, uint64_t* d_hists, const tsa_tune* tune, void* d_ws,
+                                size_t ws_bytes, hipStream_t s);
+
+// ---- graph cache -------------------------------------------------------------
+// The launch sequence of one argument set (clears, plan, scan, persistent
+// kernel, final check) is captured once into a HIP graph on a private stream
+// and replayed on the caller's stream afterwards.  Entries are keyed by every
+// argument; the cache keeps the most recent kGraphCap of them.
+namespace {
+constexpr size_t kGraphCap = 256;
+struct GraphKey {
+  uintptr_t v[16];
+  bool operator==(const GraphKey& o) const { return memcmp(v, o.v, sizeof(v)) == 0; }
+};
+struct GraphEntry {
+  GraphKey key;
+  hipGraphExec_t exec;
+  uint64_t used;
+};
+struct GraphCache {
+  std::mutex mu;
+  std::vector<GraphEntry> entries;
+  uint64_t clock = 0;
+};
+GraphCache& graphs() {
+  static GraphCache g;
+  return g;
+}
+bool graphs_enabled() {
+  static const bool on = [] {
+    const char* e = getenv("TSA_GRAPH");
+    return !(e && e[0] == '0');
+  }();
+  return on;
+}
+}  // namespace
+
 int run_region_batch(const tsa_cube* cube, const tsa_region* d_regions, int32_t nq, int32_t nbins,
                      tsa_result* d_results, uint64_t* d_hists, const tsa_tune* tune, void* d_ws, size_t ws_bytes,
                      tsa_stream_t stream) {
+  int st = check_cube(cube);
+  if (st) return st;
+  if (!d_regions || !d_results || !d_hists || nq < 1 || nq > kMaxQueries || nbins < 1 || nbins > 4096)
+    return TSA_EINVAL;
+  if (!d_ws || ws_bytes < batch_layout(nq).total) return TSA_ENOMEM;
+  hipStream_t s = (hipStream_t)stream;
+  if (!graphs_enabled() || trace_active())
+    return enqueue_region_batch(cube, d_regions, nq, nbins, d_results, d_hists, tune, d_ws, ws_bytes, s);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return TSA_EDEVICE;
+  GraphKey key;
+  memset(&key, 0, sizeof(key));
+  key.v[0] = (uintptr_t)cube->data;
+  key.v[1] = (uintptr_t)cube->dtype;
+  key.v[2] = (uintptr_t)cube->nx;
+  key.v[3] = (uintptr_t)cube->ny;
+  key.v[4] = (uintptr_t)cube->nz;
+  key.v[5] = (uintptr_t)d_regions;
+  key.v[6] = (uintptr_t)nq;
+  key.v[7] = (uintptr_t)nbins;
+  key.v[8] = (uintptr_t)d_results;
+  key.v[9] = (uintptr_t)d_hists;
+  key.v[10] = (uintptr_t)d_ws;
+  key.v[11] = (uintptr_t)ws_bytes;
+  key.v[12] = (uintptr_t)dev;
+  if (tune) {
+    key.v[13] = ((uintptr_t)(uint32_t)tune->tile_voxels << 32) | (uint32_t)tune->block_threads;
+    key.v[14] = ((uintptr_t)(uint32_t)tune->blocks_per_cu << 32) | (uint32_t)tune->cand_max;
+    key.v[15] = 1;
+  }
+  GraphCache& G = graphs();
+  {
+    std::lock_guard<std::mutex> g(G.mu);
+    for (GraphEntry& e : G.entries) {
+      if (e.key == key) {
+        e.used = ++G.clock;
+        return hipGraphLaunch(e.exec, s) == hipSuccess ? TSA_OK : TSA_EDEVICE;
+      }
+    }
+  }
+  thread_local hipStream_t cap = nullptr;
+  if (!cap && hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return TSA_EDEVICE;
+  if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return TSA_EDEVICE;
+  st = enqueue_region_batch(cube, d_regions, nq, nbins, d_results, d_hists, tune, d_ws, ws_bytes, cap);
+  hipGraph_t graph = nullptr;
+  const bool ended = hipStreamEndCapture(cap, &graph) == hipSuccess;
+  if (st != TSA_OK || !ended || !graph) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st != TSA_OK ? st : TSA_EDEVICE;
+  }
+  hipGraphExec_t exec = nullptr;
+  const bool inst = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+  (void)hipGraphDestroy(graph);
+  if (!inst) return TSA_EDEVICE;
+  {
+    std::lock_guard<std::mutex> g(G.mu);
+    if (G.entries.size() >= kGraphCap) {
+      size_t victim = 0;
+      for (size_t i = 1; i < G.entries.size(); ++i)
+        if (G.entries[i].used < G.entries[victim].used) victim = i;
+      (void)hipGraphExecDestroy(G.entries[victim].exec);
+      G.entries.erase(G.entries.begin() + victim);
+    }
+    G.entries.push_back(GraphEntry{key, exec, ++G.clock});
+  }
+  return hipGraphLaunch(exec, s) == hipSuccess ? TSA_OK : TSA_EDEVICE;
+}
+
+static int enqueue_region_batch(const tsa_cube* cube, const tsa_region* d_regions, int32_t nq, int32_t nbins,
+                                tsa_result* d_results, uint64_t* d_hists, const tsa_tune* tune, void* d_ws,
+                                size_t ws_bytes, hipStream_t s) {
   int st = check_cube(cube);
   if (st) return st;
   if (!d_regions || !d_results || !d_hists || nq < 1 || nq > kMaxQueries || nbins < 1 || nbins > 4096)
@@ -832,7 +944,6 @@ int run_region_batch(const tsa_cube* cube, const tsa_region* d_regions, int32_t 
   a.parts2 = (float2*)(ws + L.parts2);
   a.digits = (uint32_t*)(ws + L.digits);
   a.pool = (uint32_t*)(ws + L.pool);
-  hipStream_t s = (hipStream_t)stream;
   const size_t lds1 = ((size_t)kBins1 + kTrash) * 4;
   const size_t lds2 = (((size_t)nbins << a.rshift) + kTrash + kBins2) * 4;
   const size_t lds = lds1 > lds2 ? lds1 : lds2;

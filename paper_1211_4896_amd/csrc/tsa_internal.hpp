@@ -34,6 +34,7 @@ struct DevInfo {
 int device_info(DevInfo* out);
 
 // Launch tracing (tsa_trace_enable / tsa_trace_read): no-ops unless enabled.
+bool trace_active();
 void trace_begin(const char* name, hipStream_t s);
 void trace_end(hipStream_t s);
 #define TSA_TRACED(NAME, S, ...) \

@@ -411,7 +411,7 @@ struct PassB {
       if (var_on) var(raw, in);
     }
   }
-  TSA_DEV void chunk() { l2.chunk(); }
+  TSA_DEV void chunk() {}
 };
 
 template <int DT, bool VEC, bool NT>

@@ -339,23 +339,21 @@ struct Digit1Acc {  // top 12 key bits of every valid element
   TSA_DEV void chunk() {}
 };
 
-// Candidate keys are staged per block in LDS and copied to the global list in
-// runs, so the global counter sees one atomic per run instead of one per wave.
-constexpr uint32_t kCandStage = 2048;  // staged keys per block
+// Candidate keys are staged per wave in LDS and copied to the global list in
+// runs of up to kWaveStage keys, so the global counter sees one atomic per run
+// instead of one per wave instruction.  Each wave owns its stage and its fill
+// word: no block barrier is needed, so the block's waves keep their loads in
+// flight.  Appends may come from divergent code; the fill word lives in LDS so
+// every lane sees the wave's latest fill, and flushes stride over whichever
+// lanes are active.
+constexpr uint32_t kWaveStage = 256;  // staged keys per wave
+constexpr int kMaxWaves = 16;
 
 struct CandShared {
-  uint32_t buf[kCandStage];
-  uint32_t cnt;        // keys claimed in buf (may exceed kCandStage)
-  uint32_t valid_end;  // buf[0, valid_end) is filled when cnt > kCandStage
-  uint32_t gbase;
+  uint32_t buf[kMaxWaves][kWaveStage];
+  // written by one lane, read by all: volatile, so no lane reuses a stale load
+  volatile uint32_t fill[kMaxWaves];
 };
-
-TSA_DEV void cand_init(CandShared& cs) {
-  if (threadIdx.x == 0) {
-    cs.cnt = 0;
-    cs.valid_end = kCandStage;
-  }
-}
 
 struct CandSink {
   CandShared* cs;
@@ -364,49 +362,54 @@ struct CandSink {
   uint32_t cap;       // global capacity
 };
 
-// Wave-aggregated append: one LDS atomic per wave; a wave that does not fit
-// in the stage writes straight to the global list.
+// Each wave clears its own fill word (before its first append).
+TSA_DEV void cand_init(CandShared& cs) {
+  if (threadIdx.x % kWave == 0) cs.fill[threadIdx.x / kWave] = 0u;
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Active lanes of a wave copy its `fill` staged keys out (one global atomic).
+TSA_DEV void cand_copy_out(const CandSink& k, uint32_t fill) {
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const uint64_t act = __ballot(true);
+  const int leader = __ffsll((unsigned long long)act) - 1;
+  const uint32_t na = (uint32_t)__popcll(act);
+  const uint32_t rank = (uint32_t)__popcll(act & ((1ull << lane) - 1ull));
+  uint32_t g = 0;
+  if (lane == leader) g = atomicAdd(k.counter, fill);
+  g = __shfl(g, leader);
+  for (uint32_t i = rank; i < fill; i += na)
+    if (g + i < k.cap) k.list[g + i] = k.cs->buf[w][i];
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Wave-aggregated append of the lanes whose flag is set.
 TSA_DEV void cand_append(bool m, uint32_t key, const CandSink& k) {
   const uint64_t bal = __ballot(m);
   if (bal == 0) return;
-  const int lane = threadIdx.x % kWave;
-  const int leader = __ffsll((unsigned long long)bal) - 1;
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const uint32_t n = (uint32_t)__popcll(bal);
-  uint32_t pos = 0;
-  if (lane == leader) {
-    pos = __hip_atomic_fetch_add(&k.cs->cnt, n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    if (pos <= kCandStage && pos + n > kCandStage) k.cs->valid_end = pos;  // the one wave that crosses the end
+  uint32_t fill = k.cs->fill[w];
+  if (fill + n > kWaveStage) {
+    cand_copy_out(k, fill);
+    fill = 0;
   }
-  pos = __shfl(pos, leader);
   const uint32_t off = (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
-  if (pos + n <= kCandStage) {
-    if (m) k.cs->buf[pos + off] = key;
-  } else {
-    uint32_t g = 0;
-    if (lane == leader) g = atomicAdd(k.counter, n);
-    g = __shfl(g, leader);
-    if (m && g + off < k.cap) k.list[g + off] = key;
-  }
+  if (m) k.cs->buf[w][fill + off] = key;
+  const uint64_t act = __ballot(true);
+  __builtin_amdgcn_wave_barrier();
+  if (lane == __ffsll((unsigned long long)act) - 1) k.cs->fill[w] = fill + n;
+  __builtin_amdgcn_wave_barrier();
 }
 
-// Whole block: copy the staged keys out when at least `threshold` are staged.
-TSA_DEV void cand_flush(const CandSink& k, uint32_t threshold) {
-  __syncthreads();
-  const uint32_t c = k.cs->cnt;
-  const uint32_t nvalid = c <= kCandStage ? c : k.cs->valid_end;
-  __syncthreads();  // every thread has read the count before any thread appends again
-  if (c == 0 || c < threshold) return;  // uniform: every thread read the same count
-  if (threadIdx.x == 0) k.cs->gbase = nvalid ? atomicAdd(k.counter, nvalid) : 0u;
-  __syncthreads();
-  const uint32_t g = k.cs->gbase;
-  for (uint32_t i = threadIdx.x; i < nvalid; i += blockDim.x)
-    if (g + i < k.cap) k.list[g + i] = k.cs->buf[i];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    k.cs->cnt = 0;
-    k.cs->valid_end = kCandStage;
-  }
-  __syncthreads();
+// Whole wave (all lanes active): copy out what is still staged.
+TSA_DEV void cand_finish(const CandSink& k) {
+  const int w = threadIdx.x / kWave;
+  const uint32_t fill = k.cs->fill[w];
+  if (fill) cand_copy_out(k, fill);
+  __builtin_amdgcn_wave_barrier();
+  if (threadIdx.x % kWave == 0) k.cs->fill[w] = 0u;
+  __builtin_amdgcn_wave_barrier();
 }
 
 template <int DT>
@@ -422,11 +425,10 @@ struct Level2Acc {  // keys inside the level-1 bucket: next 12 bits, optional co
     if (m) lds_inc(lds, (key >> kShift2) & 0xFFFu);
     if (compact) cand_append(m, key, sink);
   }
-  TSA_DEV void chunk() {
-    if (compact) cand_flush(sink, kCandStage / 2);
-  }
+  TSA_DEV void chunk() {}
+  // every wave copies what it still holds (call with every lane active)
   TSA_DEV void finish() {
-    if (compact) cand_flush(sink, 1);
+    if (compact) cand_finish(sink);
   }
 };
 

@@ -239,19 +239,25 @@ bool launch(tsa_server* s) {
       keep.pop_back();
     }
     const int nq = (int)L.items.size();
+    // pad to a power of two with empty boxes (rejected at once by the planner),
+    // so each lane replays a handful of captured launch graphs
+    int nq_pad = 1;
+    while (nq_pad < nq) nq_pad <<= 1;
+    if (nq_pad > s->cfg.max_batch) nq_pad = s->cfg.max_batch;
     const double t = now_s();
     for (int i = 0; i < nq; ++i) {
       L.h_regions[i] = L.items[i]->req.region;
       L.items[i]->resp.t_launch = t;
     }
+    for (int i = nq; i < nq_pad; ++i) L.h_regions[i] = tsa_region{0, 0, 0, 0, 0, 0};
     const CubeRec& c = s->cubes[cube];
-    int st = hipMemcpyAsync(L.d_regions, L.h_regions, sizeof(tsa_region) * nq, hipMemcpyHostToDevice, L.stream) ==
-                     hipSuccess
+    int st = hipMemcpyAsync(L.d_regions, L.h_regions, sizeof(tsa_region) * nq_pad, hipMemcpyHostToDevice,
+                            L.stream) == hipSuccess
                  ? TSA_OK
                  : TSA_EDEVICE;
     if (st == TSA_OK)
-      st = run_region_batch(&c.cube, L.d_regions, nq, s->cfg.region_nbins, L.d_results, L.d_hists, nullptr, L.d_ws,
-                            L.ws_bytes, (tsa_stream_t)L.stream);
+      st = run_region_batch(&c.cube, L.d_regions, nq_pad, s->cfg.region_nbins, L.d_results, L.d_hists, nullptr,
+                            L.d_ws, L.ws_bytes, (tsa_stream_t)L.stream);
     if (st == TSA_OK &&
         (hipMemcpyAsync(L.h_results, L.d_results, sizeof(tsa_result) * nq, hipMemcpyDeviceToHost, L.stream) !=
              hipSuccess ||

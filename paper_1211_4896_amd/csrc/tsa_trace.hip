@@ -34,6 +34,8 @@ TraceState& T() {
 }
 }  // namespace
 
+bool trace_active() { return T().on; }
+
 void trace_begin(const char* name, hipStream_t s) {
   TraceState& t = T();
   if (!t.on) return;
