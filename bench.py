@@ -245,17 +245,32 @@ def _region_batch_bench(tsa, torch, np, synth, reps: int) -> dict:
 
     batch()
     torch.cuda.synchronize()
-    lib = api.lib
-    _trace(lib, True, cap=reps * 16)
+    # untuned (library defaults), then the autotuner's choice for this batch
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
         batch()
     e1.record()
     torch.cuda.synchronize()
+    default_ms = e0.elapsed_time(e1) / reps
+    t0 = time.perf_counter()
+    best, best_ms = tsa.tune_region_batch(dev, d_boxes, nbins, reps=2)
+    t_tune = time.perf_counter() - t0
+    batch()  # the tuned choice is now the library's choice for this shape class
+    torch.cuda.synchronize()
+    lib = api.lib
+    e0.record()
+    for _ in range(reps):
+        batch()  # replays of the captured launch graph
+    e1.record()
+    torch.cuda.synchronize()
+    b_ms = e0.elapsed_time(e1) / reps
+    _trace(lib, True, cap=reps * 16)  # eager launches, each kernel bracketed by events
+    for _ in range(reps):
+        batch()
+    torch.cuda.synchronize()
     kern = _trace_read(lib)
     _trace(lib, False)
-    b_ms = e0.elapsed_time(e1) / reps
     res = tsa.results_to_numpy(res_buf)
     bad = int(np.count_nonzero(res["status"] != 0))
     phase3 = int(np.count_nonzero(res["flags"] & tsa.FLAG_PHASE3))
@@ -301,7 +316,11 @@ def _region_batch_bench(tsa, torch, np, synth, reps: int) -> dict:
             "persistent_kernel_ms": round(batch_kernel_ms, 3),
             "hbm_frac_2_passes": round(2 * 4.0 * vox / (batch_kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "kernels_ms": {k: round(v[1] / v[0], 4) for k, v in kern.items()},
-            "status_errors": bad, "phase3_queries": phase3, "generate_s": round(t_gen, 1)}
+            "status_errors": bad, "phase3_queries": phase3, "generate_s": round(t_gen, 1),
+            "untuned_ms": round(default_ms, 3), "tuned": {"tile_voxels": best[0], "block_threads": best[1],
+                                                          "blocks_per_cu": best[2], "cand_max": best[3],
+                                                          "tuner_best_ms": round(best_ms, 3),
+                                                          "tuning_s": round(t_tune, 1)}}
 
 
 def _serving_bench(torch, np, synth, seconds: float, qps: float) -> dict:
@@ -339,7 +358,21 @@ def _serving_bench(torch, np, synth, seconds: float, qps: float) -> dict:
         st = srv.stats()
     finally:
         srv.close()
+    # capacity of the full-cube lane: one call of each full request kind per cube, alone
+    import paper_1211_4896_amd as tsa
+    single = {}
+    for nm, d in zip(names, devs):
+        mo = tsa.moments(d)
+        for kind, f in (("hist", lambda: tsa.histogram(d, float(np.float32(mo["min"])), float(np.float32(mo["max"])),
+                                                       4096)),
+                        ("median", lambda: tsa.median(d))):
+            f()
+            t0 = time.perf_counter()
+            f()
+            single[f"{nm}_{kind}_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
     keep = [o for o, t in zip(out, t_arr) if t >= warm]
+    svc = np.array([o.t_done - o.t_launch for o in keep]) * 1e3
+    qwait = np.array([o.t_launch - o.t_submit for o in keep]) * 1e3
     lat = np.array([o.t_done - o.t_submit for o in keep]) * 1e3
     kinds = np.array([o.kind for o in keep])
     t_first = min(o.t_submit for o in keep)
@@ -356,7 +389,9 @@ def _serving_bench(torch, np, synth, seconds: float, qps: float) -> dict:
             "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "p999_ms": pct(lat, 99.9),
             "p50_region_ms": pct(lat[kinds == 0], 50), "p99_region_ms": pct(lat[kinds == 0], 99),
             "p50_full_ms": pct(lat[kinds != 0], 50), "p99_full_ms": pct(lat[kinds != 0], 99),
-            "errors": errs, "scheduler": st}
+            "errors": errs, "scheduler": st,
+            "service_p50_region_ms": pct(svc[kinds == 0], 50), "service_p50_full_ms": pct(svc[kinds != 0], 50),
+            "queue_p50_full_ms": pct(qwait[kinds != 0], 50), "single_call_ms": single}
 
 
 def _calib_copy(lib, device, sh, nbytes: int = 1 << 30) -> int:

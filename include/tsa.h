@@ -174,6 +174,27 @@ int tsa_region_batch(const tsa_cube* cube, const tsa_region* d_regions, int32_t 
                      tsa_result* d_results, uint64_t* d_hists, const tsa_tune* tune, void* d_ws,
                      size_t ws_bytes, tsa_stream_t stream);
 
+/*
+ * Autotuner of tsa_region_batch: runs the caller's batch (same arguments as
+ * tsa_region_batch; outputs are overwritten) under a grid of launch choices
+ * (tile size x persistent blocks per compute unit), `reps` timed runs each
+ * after one warm-up, and writes the fastest to *best (and its mean time in
+ * milliseconds to *best_ms, if not NULL).  The choice is remembered for the
+ * batch's shape class (device architecture, dtype, nbins, log2 nq) and used by
+ * later tsa_region_batch calls with tune == NULL.  Synchronizes the stream.
+ */
+int tsa_tune_region_batch(const tsa_cube* cube, const tsa_region* d_regions, int32_t nq, int32_t nbins,
+                          tsa_result* d_results, uint64_t* d_hists, void* d_ws, size_t ws_bytes,
+                          tsa_stream_t stream, int32_t reps, tsa_tune* best, float* best_ms);
+
+/* Write the remembered tuning choices as JSON to `path` (host file).  The
+ * library also loads the file named by the environment variable
+ * TSA_TUNE_CACHE, if set, before its first lookup. */
+int tsa_tune_save(const char* path);
+
+/* Merge the choices saved in `path`; returns how many were read, or TSA_EINVAL. */
+int tsa_tune_load(const char* path);
+
 /* Human-readable text for a tsa_status value (static storage). */
 const char* tsa_status_string(int32_t status);
 

@@ -13,7 +13,9 @@
  *     run (continuous batching: requests arriving mid-flight join the next
  *     batch instead of waiting for the queue to drain);
  *   - runs full-cube histogram and median requests on a stream of their own,
- *     overlapping the region batches on the device;
+ *     overlapping the region batches on the device; every full-cube request
+ *     admitted for one cube is answered by one shared scan of that cube (one
+ *     histogram pass, the two radix passes, or the fused two-pass trio);
  *   - retires finished work by polling events and timestamps every stage.
  * Each request's result depends only on its own cube and box, never on what
  * else is in flight.

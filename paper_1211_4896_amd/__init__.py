@@ -83,6 +83,10 @@ class _CAPI:
             "tsa_status_string": (ctypes.c_char_p, [I32]),
             "tsa_version": (ctypes.c_char_p, []),
             "tsa_internal_magic_div": (ctypes.c_uint32, [ctypes.c_uint32, ctypes.c_uint32]),
+            "tsa_tune_region_batch": (ctypes.c_int, [CP, P, I32, I32, P, P, P, SZ, P, I32, ctypes.POINTER(Tune),
+                                                     ctypes.POINTER(ctypes.c_float)]),
+            "tsa_tune_save": (ctypes.c_int, [ctypes.c_char_p]),
+            "tsa_tune_load": (ctypes.c_int, [ctypes.c_char_p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -258,6 +262,25 @@ def region_batch(t, regions, nbins: int, tune: Optional[Sequence[int]] = None, s
                                    ws.data_ptr(), ws.numel(), _stream(stream)), "tsa_region_batch")
     torch.cuda.synchronize(t.device)
     return results_to_numpy(out), hists
+
+
+def tune_region_batch(t, regions, nbins: int, reps: int = 3, stream=None):
+    """Run the autotuner on this batch; returns ((tile_voxels, block_threads,
+    blocks_per_cu, cand_max), best ms).  Later region_batch calls of the same
+    shape class use the choice when no tune is given."""
+    torch = _torch()
+    c = cube_of(t)
+    reg = torch.as_tensor(regions, dtype=torch.int64).to(t.device).contiguous()
+    nq = reg.shape[0]
+    ws = workspace(OP_REGION_BATCH, t, None, nbins, nq)
+    out = torch.empty(72 * nq, dtype=torch.uint8, device=t.device)
+    hists = torch.empty((nq, nbins), dtype=torch.int64, device=t.device)
+    best = Tune()
+    ms = ctypes.c_float()
+    _check(capi().tsa_tune_region_batch(ctypes.byref(c), reg.data_ptr(), nq, nbins, out.data_ptr(), hists.data_ptr(),
+                                        ws.data_ptr(), ws.numel(), _stream(stream), reps, ctypes.byref(best),
+                                        ctypes.byref(ms)), "tsa_tune_region_batch")
+    return (best.tile_voxels, best.block_threads, best.blocks_per_cu, best.cand_max), ms.value
 
 
 def version() -> str:

@@ -26,8 +26,8 @@
 namespace tsa {
 
 constexpr uint32_t kDefTileUnits = 16384;  // 16-byte vectors per tile (64K float32 voxels)
-constexpr uint32_t kDefCandMax = 65536;    // largest first-digit bucket copied out
-constexpr uint32_t kPoolKeys = 1u << 23;   // candidate pool (keys) shared by the batch
+constexpr uint32_t kDefCandMax = 1u << 20;  // largest first-digit bucket copied out
+constexpr uint32_t kPoolPerQuery = 16384;   // candidate pool keys per query (shared by the batch)
 constexpr int kBBlock = 256;
 constexpr int kMaxQueries = 65536;
 constexpr uint32_t kSpinLimit = 1u << 24;        // polls per wait, at most
@@ -70,6 +70,7 @@ struct BArgs {
   QGeom* geom;
   QState* st;
   uint64_t* tile_base;
+  uint32_t* tile_q;  // ticket (tile of the batch) -> query
   Partial* parts1;
   float2* parts2;
   uint32_t* digits;
@@ -181,8 +182,10 @@ __global__ __launch_bounds__(1024) void k_bscan(BArgs a) {
   }
   for (int i = 0; i < per; ++i) {
     if (q0 + i < a.nq) {
+      const uint32_t nt = a.geom[q0 + i].ntiles;
       a.tile_base[q0 + i] = base;
-      base += a.geom[q0 + i].ntiles;
+      for (uint32_t k = 0; k < nt; ++k) a.tile_q[base + k] = (uint32_t)(q0 + i);
+      base += nt;
     }
   }
   if (t == 0) {
@@ -620,18 +623,11 @@ __global__ __launch_bounds__(kBBlock) void k_batch(BArgs a) {
       if (!block_wait_ge(&a.hdr->p2_done, (uint32_t)a.nq, &a.hdr->err, sh)) return;
       if (__hip_atomic_load(&a.hdr->any3, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0 || lt >= T1) return;
     }
-    // ticket -> (query, tile): binary search over the tile prefix sums
+    // ticket -> (query, tile)
     if (t == 0) {
-      uint32_t lo = 0, hi = (uint32_t)a.nq;  // tile_base[lo] <= lt < tile_base[hi]
-      while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (a.tile_base[mid] <= lt)
-          lo = mid;
-        else
-          hi = mid;
-      }
-      sh.q = lo;
-      sh.tile = (uint32_t)(lt - a.tile_base[lo]);
+      const uint32_t qq = a.tile_q[lt];
+      sh.q = qq;
+      sh.tile = (uint32_t)(lt - a.tile_base[qq]);
     }
     __syncthreads();
     const uint32_t q = sh.q, tile = sh.tile;
@@ -717,11 +713,11 @@ __global__ __launch_bounds__(kBBlock) void k_batch(BArgs a) {
     // count the tile; the block finishing the last one runs the epilogue
     __syncthreads();
     if (t == 0) {
-      __threadfence();
+      __threadfence();  // publish this tile's partial before counting it
       uint32_t* cnt = phase == 1 ? &s.done1 : phase == 2 ? &s.done2 : &s.done3;
       const uint32_t prev = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
       sh.last = prev + 1 == g.ntiles ? 1u : 0u;
-      __threadfence();
+      if (sh.last) __threadfence();  // the epilogue reads every tile's partial
     }
     __syncthreads();
     if (sh.last) {
@@ -747,8 +743,8 @@ __global__ void k_bfinal(BArgs a) {
 // host side
 // ---------------------------------------------------------------------------
 struct BLayout {
-  size_t hdr, geom, st, tile_base, parts1, parts2, digits, pool, total;
-  uint32_t max_tiles;
+  size_t hdr, geom, st, tile_base, tile_q, parts1, parts2, digits, pool, total;
+  uint32_t max_tiles, pool_keys;
 };
 
 static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -768,14 +764,20 @@ static BLayout batch_layout(int32_t nq) {
   o = al(o + sizeof(QState) * (size_t)nq);
   L.tile_base = o;
   o = al(o + 8 * ((size_t)nq + 1));
+  L.tile_q = o;
+  o = al(o + 4 * (size_t)nq * mt);
   L.parts1 = o;
   o = al(o + sizeof(Partial) * (size_t)nq * mt);
   L.parts2 = o;
   o = al(o + sizeof(float2) * (size_t)nq * mt);
   L.digits = o;
   o = al(o + 4 * (size_t)kBins1 * nq);
+  uint64_t pk = (uint64_t)kPoolPerQuery * (uint64_t)nq;
+  if (pk < (1ull << 20)) pk = 1ull << 20;
+  if (pk > (1ull << 28)) pk = 1ull << 28;
+  L.pool_keys = (uint32_t)pk;
   L.pool = o;
-  o = al(o + 4 * (size_t)kPoolKeys);
+  o = al(o + 4 * (size_t)pk);
   L.total = o;
   return L;
 }
@@ -790,6 +792,7 @@ static void bfill(void* p, size_t words, hipStream_t s);
 static int enqueue_region_batch(const tsa_cube* cube, const tsa_region* d_regions, int32_t nq, int32_t nbins,
                                 tsa_result* d_results, uint64_t* d_hists, const tsa_tune* tune, void* d_ws,
                                 size_t ws_bytes, hipStream_t s);
+bool tune_lookup(const tsa_cube* cube, int32_t nbins, int32_t nq, tsa_tune* out);
 
 // ---- graph cache -------------------------------------------------------------
 // The launch sequence of one argument set (clears, plan, scan, persistent
@@ -834,6 +837,8 @@ int run_region_batch(const tsa_cube* cube, const tsa_region* d_regions, int32_t 
     return TSA_EINVAL;
   if (!d_ws || ws_bytes < batch_layout(nq).total) return TSA_ENOMEM;
   hipStream_t s = (hipStream_t)stream;
+  tsa_tune tuned;
+  if (!tune && tune_lookup(cube, nbins, nq, &tuned)) tune = &tuned;
   if (!graphs_enabled() || trace_active())
     return enqueue_region_batch(cube, d_regions, nq, nbins, d_results, d_hists, tune, d_ws, ws_bytes, s);
   int dev = 0;
@@ -932,7 +937,7 @@ static int enqueue_region_batch(const tsa_cube* cube, const tsa_region* d_region
   a.tile_units = tile_units;
   a.max_tiles = L.max_tiles;
   a.cand_max = cand_max;
-  a.pool_keys = kPoolKeys;
+  a.pool_keys = L.pool_keys;
   a.vec = vec ? 1 : 0;
   a.results = d_results;
   a.hists = d_hists;
@@ -940,6 +945,7 @@ static int enqueue_region_batch(const tsa_cube* cube, const tsa_region* d_region
   a.geom = (QGeom*)(ws + L.geom);
   a.st = (QState*)(ws + L.st);
   a.tile_base = (uint64_t*)(ws + L.tile_base);
+  a.tile_q = (uint32_t*)(ws + L.tile_q);
   a.parts1 = (Partial*)(ws + L.parts1);
   a.parts2 = (float2*)(ws + L.parts2);
   a.digits = (uint32_t*)(ws + L.digits);

@@ -11,54 +11,6 @@
 
 namespace tsa {
 
-struct Hist16Acc {
-  uint32_t* lds;
-  float lo, hi, scale;
-  int32_t nbm1, b0, nb;
-  uint64_t* counts;
-  uint32_t epoch, chunks;
-  bool count_out;
-  uint32_t below, above;
-
-  template <class T>
-  TSA_DEV void operator()(T raw, bool in) {
-    const float v = (float)raw;
-    if (count_out) {
-      below += (in && v < lo) ? 1u : 0u;
-      above += (in && v > hi) ? 1u : 0u;
-    }
-    if (in && v >= lo && v <= hi) {
-      const float d = v - lo;
-      const float t = d * scale;
-      const int32_t b = min(max((int32_t)t, 0), nbm1);
-      const uint32_t rel = (uint32_t)(b - b0);
-      if (rel < (uint32_t)nb)
-        __hip_atomic_fetch_add(lds + (rel >> 1), 1u << ((rel & 1u) * 16u), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_WORKGROUP);
-    }
-  }
-  TSA_DEV void flush() {
-    __syncthreads();
-    const uint32_t words = ((uint32_t)nb + 1u) >> 1;
-    for (uint32_t w = threadIdx.x; w < words; w += blockDim.x) {
-      const uint32_t x = lds[w];
-      if (x) {
-        const uint32_t c0 = x & 0xFFFFu, c1 = x >> 16;
-        if (c0) atomicAdd((unsigned long long*)(counts + b0 + 2 * w), (unsigned long long)c0);
-        if (c1) atomicAdd((unsigned long long*)(counts + b0 + 2 * w + 1), (unsigned long long)c1);
-        lds[w] = 0u;
-      }
-    }
-    __syncthreads();
-  }
-  TSA_DEV void chunk() {
-    if (++chunks == epoch) {
-      chunks = 0;
-      flush();
-    }
-  }
-};
-
 template <int DT, bool VEC, bool NT>
 __global__ __launch_bounds__(1024) void k_hist16(Geom g, float lo, float hi, float scale, int32_t nbins, int32_t b0,
                                                  int32_t nb, uint32_t epoch, uint64_t* __restrict__ counts,

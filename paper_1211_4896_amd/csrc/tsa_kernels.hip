@@ -445,6 +445,58 @@ __global__ __launch_bounds__(1024) void k_pass_b(Geom g, int32_t nbins, uint32_t
   if (var_on) block_store_var(b.var, sm, parts2 + blockIdx.x);
 }
 
+// Pass B with 16-bit histogram counters (nbins too large for 32-bit LDS
+// counters): the histogram flushes its counters every `epoch` chunks.
+template <int DT>
+struct PassB16 {
+  Hist16Acc h;
+  Level2Acc<DT> l2;
+  VarAcc var;
+  bool hist_on, var_on;
+  template <class T>
+  TSA_DEV void operator()(T raw, bool in) {
+    if (hist_on) h(raw, in);
+    l2(raw, in);
+    if constexpr (DT == 0) {
+      if (var_on) var(raw, in);
+    }
+  }
+  TSA_DEV void chunk() {
+    if (hist_on) h.chunk();
+  }
+};
+
+template <int DT, bool VEC, bool NT>
+__global__ __launch_bounds__(1024) void k_pass_b16(Geom g, int32_t nbins, uint32_t epoch, SelState* __restrict__ st,
+                                                   uint64_t* __restrict__ counts, uint64_t* __restrict__ outl,
+                                                   uint64_t* __restrict__ hist2, uint32_t* __restrict__ cand,
+                                                   Partial* __restrict__ parts2) {
+  extern __shared__ uint32_t lds[];  // [(nbins+1)/2] 16-bit counter pairs, then [kBins2] level-2 digits
+  __shared__ uint32_t osm[32];
+  __shared__ MomShared sm;
+  __shared__ CandShared cs;
+  const uint32_t hwords = ((uint32_t)nbins + 1u) >> 1;
+  uint32_t* l2 = lds + hwords;
+  const bool hist_on = st->hist_ok != 0;
+  const bool sel_on = st->done == 0;
+  const bool var_on = DT == 0 && st->var_on != 0;
+  if (!hist_on && !sel_on && !var_on) return;
+  lds_zero(lds, hwords + kBins2);
+  cand_init(cs);
+  __syncthreads();
+  PassB16<DT> b{Hist16Acc{lds, st->lo, st->hi, st->scale, nbins - 1, 0, nbins, counts, epoch, 0u, true, 0u, 0u},
+                Level2Acc<DT>{l2, sel_on ? (st->prefix >> kShift1) : 0xFFFFFFFFu, sel_on && st->compact != 0,
+                              CandSink{&cs, cand, &st->ncand, st->cand_cap}},
+                VarAcc{st->shift, st->vscale}, hist_on, var_on};
+  walk<DT, VEC, kUnroll, NT>(g, b);
+  b.l2.finish();
+  if (hist_on) b.h.flush();
+  __syncthreads();
+  if (sel_on) lds_flush(l2, kBins2, 0, hist2);
+  if (hist_on) block_add_outliers(b.h.below, b.h.above, outl, osm);
+  if (var_on) block_store_var(b.var, sm, parts2 + blockIdx.x);
+}
+
 // M2 about the shift c: M2 = sum (x-c)^2 - n (mean - c)^2, block partials
 // added in a fixed order (strided per thread, then a pairwise tree).
 __global__ __launch_bounds__(1024) void k_var_finish(const Partial* __restrict__ parts2, int np,
@@ -747,6 +799,19 @@ static void reset_select(const Prep& P) {
   fill32(P.ws + P.L.state + offsetof(SelState, cand_cap), 1, P.L.cand_cap, P.s);
 }
 
+template <int DT, bool VEC, bool NT>
+static int launch_pass_b16(const Prep& P, int block, int grid, size_t lds, int32_t nbins, uint32_t epoch,
+                           SelState* stp, uint64_t* d_counts, uint64_t* outl, uint64_t* h2, uint32_t* cand,
+                           Partial* parts2) {
+  if (lds > 65536 && hipFuncSetAttribute((const void*)k_pass_b16<DT, VEC, NT>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return TSA_EDEVICE;
+  TSA_TRACED("pass_b16", P.s,
+             hipLaunchKernelGGL((k_pass_b16<DT, VEC, NT>), dim3(grid), dim3(block), lds, P.s, P.g, nbins, epoch, stp,
+                                d_counts, outl, h2, cand, parts2));
+  return TSA_OK;
+}
+
 int run_moments(const tsa_cube* cube, const tsa_region* region, tsa_result* d_out, void* d_ws, size_t ws_bytes,
                 tsa_stream_t stream) {
   if (!d_out) return TSA_EINVAL;
@@ -846,7 +911,10 @@ int run_stats(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa
   int st = prepare(cube, region, d_ws, ws_bytes, stream, &P);
   if (st) return st;
   const size_t budget = P.dev.lds_per_block < 65536 ? P.dev.lds_per_block : 65536;
-  if (((size_t)nbins + kTrash + kBins2) * 4 > budget) return TSA_ENOTSUP;
+  const bool wide = ((size_t)nbins + kTrash + kBins2) * 4 > budget;
+  // 16-bit counters: (nbins+1)/2 words + level-2 digits, plus ~10 KB of static LDS
+  const size_t lds16 = ((((size_t)nbins + 1) / 2) + kBins2) * 4;
+  if (wide && lds16 + 10240 > P.dev.lds_per_block) return TSA_ENOTSUP;
   reset_select(P);
   uint64_t* outl = d_outliers ? d_outliers : (uint64_t*)(P.ws + P.L.outl);
   fill32(d_counts, (size_t)nbins * 2, 0u, P.s);
@@ -864,15 +932,32 @@ int run_stats(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa
   TSA_TRACED("mid", P.s,
              hipLaunchKernelGGL(k_mid, dim3(1), dim3(1024), 0, P.s, (const Partial*)parts, P.grid, cube->dtype,
                                 (uint64_t)P.volume, nbins, (const uint64_t*)h1, stp, d_out));
-  uint32_t rsb = rep_shift_for(nbins, budget - (kBins2 + kTrash) * 4);
-  const size_t ldsb = (((size_t)nbins << rsb) + kTrash + kBins2) * 4;
   Partial* parts2 = (Partial*)(P.ws + P.L.partials2);
-  TSA_TRACED("pass_b", P.s,
+  int np2 = P.grid;
+  if (!wide) {
+    uint32_t rsb = rep_shift_for(nbins, budget - (kBins2 + kTrash) * 4);
+    const size_t ldsb = (((size_t)nbins << rsb) + kTrash + kBins2) * 4;
+    TSA_TRACED("pass_b", P.s,
+      TSA_DISPATCH(cube->dtype, P.vec, tuning().nt,
+                   hipLaunchKernelGGL((k_pass_b<DT, VEC, NT>), dim3(P.grid), dim3(P.block), ldsb, P.s, P.g, nbins,
+                                      rsb, stp, d_counts, outl, h2, cand, parts2)));
+  } else {
+    // one 1024-thread block per compute unit holds the 16-bit counters
+    const int blk = 1024;
+    int grid = P.dev.cus;
+    if (grid > P.grid) grid = P.grid;
+    np2 = grid;
+    const int epv = P.vec ? (cube->dtype == TSA_F32 ? 4 : 8) : 1;
+    const int64_t ep = (65535 - 16) / ((int64_t)blk * kUnroll * epv);
+    if (ep < 1) return TSA_ENOTSUP;
+    int st2 = TSA_OK;
     TSA_DISPATCH(cube->dtype, P.vec, tuning().nt,
-                 hipLaunchKernelGGL((k_pass_b<DT, VEC, NT>), dim3(P.grid), dim3(P.block), ldsb, P.s, P.g, nbins, rsb,
-                                    stp, d_counts, outl, h2, cand, parts2)));
+                 st2 = (launch_pass_b16<DT, VEC, NT>(P, blk, grid, lds16, nbins, (uint32_t)ep, stp, d_counts, outl,
+                                                     h2, cand, parts2)));
+    if (st2) return st2;
+  }
   TSA_TRACED("var_finish", P.s,
-             hipLaunchKernelGGL(k_var_finish, dim3(1), dim3(1024), 0, P.s, (const Partial*)parts2, P.grid,
+             hipLaunchKernelGGL(k_var_finish, dim3(1), dim3(1024), 0, P.s, (const Partial*)parts2, np2,
                                 (const SelState*)stp, d_out));
   return launch_median_tail(cube, P, d_out, false);
 }

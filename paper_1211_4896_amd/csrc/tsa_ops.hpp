@@ -300,6 +300,59 @@ struct HistAcc {
   TSA_DEV void chunk() {}
 };
 
+// ---- histogram with 16-bit LDS counters (up to 65536 bins) ---------------------
+// Bins [b0, b0+nb) live as 16-bit halves of LDS words; every `epoch` calls of
+// chunk() the block adds its non-zero counters to the global uint64 bins and
+// clears them, so no half can carry into its neighbour (the caller bounds the
+// elements per epoch by 65535).
+struct Hist16Acc {
+  uint32_t* lds;
+  float lo, hi, scale;
+  int32_t nbm1, b0, nb;
+  uint64_t* counts;
+  uint32_t epoch, chunks;
+  bool count_out;
+  uint32_t below, above;
+
+  template <class T>
+  TSA_DEV void operator()(T raw, bool in) {
+    const float v = (float)raw;
+    if (count_out) {
+      below += (in && v < lo) ? 1u : 0u;
+      above += (in && v > hi) ? 1u : 0u;
+    }
+    if (in && v >= lo && v <= hi) {
+      const float d = v - lo;
+      const float t = d * scale;
+      const int32_t b = min(max((int32_t)t, 0), nbm1);
+      const uint32_t rel = (uint32_t)(b - b0);
+      if (rel < (uint32_t)nb)
+        __hip_atomic_fetch_add(lds + (rel >> 1), 1u << ((rel & 1u) * 16u), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+  }
+  TSA_DEV void flush() {
+    __syncthreads();
+    const uint32_t words = ((uint32_t)nb + 1u) >> 1;
+    for (uint32_t w = threadIdx.x; w < words; w += blockDim.x) {
+      const uint32_t x = lds[w];
+      if (x) {
+        const uint32_t c0 = x & 0xFFFFu, c1 = x >> 16;
+        if (c0) atomicAdd((unsigned long long*)(counts + b0 + 2 * w), (unsigned long long)c0);
+        if (c1) atomicAdd((unsigned long long*)(counts + b0 + 2 * w + 1), (unsigned long long)c1);
+        lds[w] = 0u;
+      }
+    }
+    __syncthreads();
+  }
+  TSA_DEV void chunk() {
+    if (++chunks == epoch) {
+      chunks = 0;
+      flush();
+    }
+  }
+};
+
 TSA_DEV void block_add_outliers(uint32_t below, uint32_t above, uint64_t* g, uint32_t* sm) {
   below = wave_sum_u32(below);
   above = wave_sum_u32(above);
@@ -346,7 +399,7 @@ struct Digit1Acc {  // top 12 key bits of every valid element
 // flight.  Appends may come from divergent code; the fill word lives in LDS so
 // every lane sees the wave's latest fill, and flushes stride over whichever
 // lanes are active.
-constexpr uint32_t kWaveStage = 256;  // staged keys per wave
+constexpr uint32_t kWaveStage = 128;  // staged keys per wave
 constexpr int kMaxWaves = 16;
 
 struct CandShared {

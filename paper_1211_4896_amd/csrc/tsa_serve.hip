@@ -68,7 +68,8 @@ struct FullLane {
   uint64_t* d_outl = nullptr;
   tsa_result* h_result = nullptr;
   uint64_t* h_counts = nullptr;
-  Item* item = nullptr;
+  std::vector<Item*> items;  // every request the current shared scan answers
+  bool has_hist = false;
   bool busy = false;
 };
 
@@ -94,7 +95,7 @@ struct tsa_server {
   std::atomic<bool> stop{false};
   std::thread th;
   // counters
-  uint64_t n_batches = 0, n_batch_items = 0, n_full = 0, max_batch_seen = 0, n_admit_waits = 0;
+  uint64_t n_batches = 0, n_batch_items = 0, n_full = 0, n_scans = 0, max_batch_seen = 0, n_admit_waits = 0;
   double busy_region_s = 0, busy_full_s = 0;
 };
 
@@ -152,27 +153,31 @@ bool retire(tsa_server* s) {
     did = true;
   }
   if (s->fl.busy && hipEventQuery(s->fl.ev) == hipSuccess) {
-    Item* it = s->fl.item;
     const double t = now_s();
-    if (it->req.kind == TSA_REQ_FULL_MEDIAN) {
-      it->resp.result = *s->fl.h_result;
-      it->resp.status = s->fl.h_result->status;
-    } else {
+    uint64_t tot = 0;
+    if (s->fl.has_hist)
+      for (int b = 0; b < s->cfg.full_nbins; ++b) tot += s->fl.h_counts[b];
+    for (Item* it : s->fl.items) {
       const CubeRec& c = s->cubes[it->req.cube];
       tsa_result r = nan_result();
-      uint64_t tot = 0;
-      for (int b = 0; b < s->cfg.full_nbins; ++b) tot += s->fl.h_counts[b];
-      r.count = tot;
-      r.min = c.lo;
-      r.max = c.hi;
+      r.status = s->fl.h_result->status;
+      if (it->req.kind == TSA_REQ_FULL_MEDIAN) {
+        r.count = s->fl.h_result->count;
+        r.nan_count = s->fl.h_result->nan_count;
+        r.median = s->fl.h_result->median;
+      } else {
+        r.count = tot;
+        r.min = c.lo;
+        r.max = c.hi;
+        if (it->req.h_hist) memcpy(it->req.h_hist, s->fl.h_counts, sizeof(uint64_t) * s->cfg.full_nbins);
+      }
       it->resp.result = r;
-      it->resp.status = TSA_OK;
-      if (it->req.h_hist) memcpy(it->req.h_hist, s->fl.h_counts, sizeof(uint64_t) * s->cfg.full_nbins);
+      it->resp.status = r.status;
+      it->resp.t_done = t;
+      release(s, it);
+      finish_item(s, it);
     }
-    it->resp.t_done = t;
-    release(s, it);
-    finish_item(s, it);
-    s->fl.item = nullptr;
+    s->fl.items.clear();
     s->fl.busy = false;
     did = true;
   }
@@ -281,36 +286,71 @@ bool launch(tsa_server* s) {
     did = true;
   }
   if (!s->fl.busy && !s->adm_full.empty()) {
-    Item* it = s->adm_full.front();
-    s->adm_full.pop_front();
-    const CubeRec& c = s->cubes[it->req.cube];
-    it->resp.t_launch = now_s();
-    int st;
-    if (it->req.kind == TSA_REQ_FULL_MEDIAN) {
-      st = run_median(&c.cube, nullptr, s->fl.d_result, s->fl.d_ws, s->fl.ws_bytes, (tsa_stream_t)s->fl.stream);
-      if (st == TSA_OK && hipMemcpyAsync(s->fl.h_result, s->fl.d_result, sizeof(tsa_result), hipMemcpyDeviceToHost,
-                                         s->fl.stream) != hipSuccess)
-        st = TSA_EDEVICE;
-    } else if (!c.range_ok) {
-      st = TSA_EINVAL;
-    } else {
-      st = run_histogram(&c.cube, nullptr, c.lo, c.hi, s->cfg.full_nbins, s->fl.d_counts, s->fl.d_outl, s->fl.d_ws,
-                         s->fl.ws_bytes, (tsa_stream_t)s->fl.stream);
-      if (st == TSA_OK &&
-          hipMemcpyAsync(s->fl.h_counts, s->fl.d_counts, sizeof(uint64_t) * s->cfg.full_nbins, hipMemcpyDeviceToHost,
-                         s->fl.stream) != hipSuccess)
-        st = TSA_EDEVICE;
+    // one shared scan answers every admitted full-cube request on the cube of
+    // the oldest one: histogram requests share one pass, median requests the
+    // two radix passes, and both kinds together the fused two-pass trio
+    const int32_t cube = s->adm_full.front()->req.cube;
+    std::deque<Item*> keep;
+    bool any_hist = false, any_median = false;
+    while (!s->adm_full.empty()) {
+      Item* it = s->adm_full.front();
+      s->adm_full.pop_front();
+      if (it->req.cube == cube) {
+        s->fl.items.push_back(it);
+        any_hist |= it->req.kind == TSA_REQ_FULL_HIST;
+        any_median |= it->req.kind == TSA_REQ_FULL_MEDIAN;
+      } else {
+        keep.push_back(it);
+      }
     }
+    while (!keep.empty()) {
+      s->adm_full.push_front(keep.back());
+      keep.pop_back();
+    }
+    const CubeRec& c = s->cubes[cube];
+    const double t = now_s();
+    for (Item* it : s->fl.items) it->resp.t_launch = t;
+    const tsa_stream_t fs = (tsa_stream_t)s->fl.stream;
+    int st = TSA_OK;
+    if (any_hist && !c.range_ok) st = TSA_EINVAL;
+    const size_t fused_lds = ((size_t)s->cfg.full_nbins + 64 + 4096) * 4;
+    if (st == TSA_OK && any_hist && any_median && fused_lds <= 65536) {
+      st = run_stats(&c.cube, nullptr, s->cfg.full_nbins, s->fl.d_result, s->fl.d_counts, s->fl.d_outl, s->fl.d_ws,
+                     s->fl.ws_bytes, fs);
+    } else {
+      if (st == TSA_OK && any_hist)
+        st = run_histogram(&c.cube, nullptr, c.lo, c.hi, s->cfg.full_nbins, s->fl.d_counts, s->fl.d_outl,
+                           s->fl.d_ws, s->fl.ws_bytes, fs);
+      if (st == TSA_OK && any_median)
+        st = run_median(&c.cube, nullptr, s->fl.d_result, s->fl.d_ws, s->fl.ws_bytes, fs);
+    }
+    if (st == TSA_OK && !any_median) {
+      tsa_result ok = nan_result();
+      *s->fl.h_result = ok;  // only histograms: no device result to copy
+    }
+    if (st == TSA_OK && any_median &&
+        hipMemcpyAsync(s->fl.h_result, s->fl.d_result, sizeof(tsa_result), hipMemcpyDeviceToHost, s->fl.stream) !=
+            hipSuccess)
+      st = TSA_EDEVICE;
+    if (st == TSA_OK && any_hist &&
+        hipMemcpyAsync(s->fl.h_counts, s->fl.d_counts, sizeof(uint64_t) * s->cfg.full_nbins, hipMemcpyDeviceToHost,
+                       s->fl.stream) != hipSuccess)
+      st = TSA_EDEVICE;
     if (st == TSA_OK && hipEventRecord(s->fl.ev, s->fl.stream) != hipSuccess) st = TSA_EDEVICE;
     if (st != TSA_OK) {
-      it->resp.result = nan_result();
-      fail_item(s, it, st);
-      release(s, it);
-      finish_item(s, it);
+      for (Item* it : s->fl.items) {
+        it->resp.result = nan_result();
+        it->resp.result.status = st;
+        fail_item(s, it, st);
+        release(s, it);
+        finish_item(s, it);
+      }
+      s->fl.items.clear();
     } else {
-      s->fl.item = it;
+      s->fl.has_hist = any_hist;
       s->fl.busy = true;
-      s->n_full++;
+      s->n_full += s->fl.items.size();
+      s->n_scans++;
     }
     did = true;
   }
@@ -553,9 +593,11 @@ int tsa_server_stats(tsa_server* s, char* buf, size_t len) {
   char tmp[512];
   const int n = snprintf(tmp, sizeof(tmp),
                          "{\"batches\": %llu, \"batched_requests\": %llu, \"max_batch\": %llu, \"full_requests\": "
-                         "%llu, \"admission_waits\": %llu, \"submitted\": %llu, \"finished\": %llu}",
+                         "%llu, \"full_scans\": %llu, \"admission_waits\": %llu, \"submitted\": %llu, "
+                         "\"finished\": %llu}",
                          (unsigned long long)s->n_batches, (unsigned long long)s->n_batch_items,
                          (unsigned long long)s->max_batch_seen, (unsigned long long)s->n_full,
+                         (unsigned long long)s->n_scans,
                          (unsigned long long)s->n_admit_waits, (unsigned long long)s->submitted,
                          (unsigned long long)s->finished);
   if (n < 0 || (size_t)n + 1 > len) return TSA_ENOMEM;

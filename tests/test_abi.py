@@ -111,3 +111,17 @@ def test_batch_workspace_bytes():
     assert 0 < n1 < n2
     assert c.tsa_workspace_bytes(tsa.OP_REGION_BATCH, ctypes.byref(cube), None, 4097, 8) == 0
     assert c.tsa_workspace_bytes(tsa.OP_REGION_BATCH, ctypes.byref(cube), None, 256, 65537) == 0
+
+
+def test_tune_cache_roundtrip(tmp_path):
+    c = tsa.capi()
+    p = tmp_path / "tune.json"
+    p.write_text('{\n  "gfx950|f32|nbins=256|nq2=12": [65536, 256, 4, 65536],\n'
+                 '  "gfx950|i16|nbins=128|nq2=3": [16384, 256, 8, 0]\n}\n')
+    assert c.tsa_tune_load(str(p).encode()) == 2
+    q = tmp_path / "out.json"
+    assert c.tsa_tune_save(str(q).encode()) == 0
+    txt = q.read_text()
+    assert '"gfx950|f32|nbins=256|nq2=12": [65536, 256, 4, 65536]' in txt
+    assert '"gfx950|i16|nbins=128|nq2=3": [16384, 256, 8, 0]' in txt
+    assert c.tsa_tune_load(str(tmp_path / "missing.json").encode()) == tsa.TSA_EINVAL

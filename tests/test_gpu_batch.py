@@ -177,3 +177,14 @@ def test_batch_graph_replays_match_eager_inputs():
             check_moments(r, want, "f32", f"replay {rep} q{i}")
             check_median(r["median"], want["median"], "f32", f"replay {rep} q{i}")
             check_hist(got[1][i].cpu().numpy().view(np.uint64), None, want["counts"], None, f"replay {rep} q{i}")
+
+
+def test_autotuner_choice_is_used_and_correct():
+    spec = synth.scaled(synth.SPECS["c1"], 128, 96, 64)
+    host, _ = synth.generate(spec)
+    dev = _dev(host)
+    boxes = _boxes((128, 96, 64), 123, 31, lo=4, hi=96)
+    _say("case batch autotuner")
+    best, ms = tsa.tune_region_batch(dev, boxes, 64, reps=1)
+    assert best[0] in (16384, 65536, 262144) and best[2] in (2, 4, 8) and ms > 0
+    _check_batch(host, dev, boxes, 64, what="tuned")  # tune=None: the remembered choice

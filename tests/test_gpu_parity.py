@@ -188,6 +188,13 @@ def test_histogram_bin_counts(nbins):
     wc, wo = oracle.histogram(host, -2.0, 20.0, nbins, b)
     c, o = tsa.histogram(dev, -2.0, 20.0, nbins, b)
     check_hist(c, o, wc, wo, f"nbins {nbins} region")
+    # the fused trio at this bin count (16-bit counters above ~12K bins)
+    for reg in (None, b):
+        want = oracle.stats(host, nbins, reg)
+        res, c, o = tsa.stats(dev, nbins, reg)
+        check_moments(res, want, "f32", f"stats nbins {nbins} {reg}")
+        check_median(res["median"], want["median"], "f32", f"stats nbins {nbins} {reg}")
+        check_hist(c, o, want["counts"], want["outliers"], f"stats nbins {nbins} {reg}")
 
 
 def test_integer_grid_histogram_is_bincount():
