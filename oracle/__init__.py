@@ -16,7 +16,13 @@ slow restatement of what the paper (arXiv 1211.4896) defines:
                   with a library selection (numpy.partition) on a copy;
 * median_sort  -- the same value by qsort, for small inputs;
 * torben       -- Appendix A, Algorithm 1 (Torben Mogensen's method), a second
-                  and independent algorithm for the same value.
+                  and independent algorithm for the same value;
+* quantile     -- the lower q-quantile, value of rank floor(q (n-1)); q = 0.5
+                  is the lower median (an arbitrary rank is the general form of
+                  the selection Section 4.3 performs);
+* mad          -- the median absolute deviation Section 4.3 names: the lower
+                  median of |x - m| with m the lower median and x - m rounded
+                  to single precision (int16: exact).
 
 NaN is the NULL value and is excluded everywhere.  The C parts live in
 tsa_oracle.c and are built with gcc by ``build()``.
@@ -224,3 +230,55 @@ def stats(a: np.ndarray, nbins: int, region=None) -> dict:
         out["hist_skipped"] = True
     out["median"], _ = median(a, region)
     return out
+
+
+def _valid_values(a: np.ndarray, region=None) -> np.ndarray:
+    v = _region_view(a, region)
+    flat = v.reshape(-1)
+    return flat[~np.isnan(flat)] if flat.dtype == np.float32 else flat
+
+
+def _select(vals: np.ndarray, k: int):
+    """Value of 0-based rank k by totalOrder (numpy.partition; signed zero as in median())."""
+    m = np.partition(vals, k)[k]
+    if vals.dtype == np.float32 and m == 0:
+        n_before = int(np.count_nonzero(vals < 0)) + int(np.count_nonzero((vals == 0) & np.signbit(vals)))
+        m = np.float32(-0.0) if k < n_before else np.float32(0.0)
+    return m
+
+
+def quantile_rank(q: float, n: int) -> int:
+    """0-based rank floor(q (n-1)), the product taken in double precision."""
+    if not (0.0 <= q <= 1.0) or n < 1:
+        raise ValueError("q must lie in [0, 1] and n >= 1")
+    k = int(np.floor(np.float64(q) * np.float64(n - 1)))
+    return min(max(k, 0), n - 1)
+
+
+def quantile(a: np.ndarray, q: float, region=None):
+    """Lower q-quantile of the non-NaN voxels: returns (value, count); NaN when empty."""
+    vals = _valid_values(a, region)
+    n = vals.size
+    if n == 0:
+        return float("nan"), 0
+    return float(_select(vals, quantile_rank(q, n))), n
+
+
+def mad(a: np.ndarray, region=None):
+    """Median absolute deviation: returns (median, mad, count).
+
+    m is the lower median; deviations |x - m| are rounded to single precision
+    for float32 cubes (numpy float32 arithmetic: one IEEE subtraction, then an
+    exact absolute value) and exact integers for int16 cubes; the MAD is their
+    lower median."""
+    vals = _valid_values(a, region)
+    n = vals.size
+    if n == 0:
+        return float("nan"), float("nan"), 0
+    k = (n - 1) // 2
+    m = _select(vals, k)
+    if vals.dtype == np.float32:
+        d = np.abs(vals - np.float32(m))
+    else:
+        d = np.abs(vals.astype(np.int32) - np.int32(m))
+    return float(m), float(np.partition(d, k)[k]), n
