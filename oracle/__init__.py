@@ -22,7 +22,12 @@ slow restatement of what the paper (arXiv 1211.4896) defines:
                   the selection Section 4.3 performs);
 * mad          -- the median absolute deviation Section 4.3 names: the lower
                   median of |x - m| with m the lower median and x - m rounded
-                  to single precision (int16: exact).
+                  to single precision (int16: exact);
+* minimap_cells, sigma_counts
+               -- Section 4.5's statistical mini-map: the cube cut into cells
+                  of cx*cy*cz voxels (the last cell along an axis keeps the
+                  remainder), each summarised by its statistics, and the local
+                  threshold: per cell, the voxels above mean + k * std.
 
 NaN is the NULL value and is excluded everywhere.  The C parts live in
 tsa_oracle.c and are built with gcc by ``build()``.
@@ -282,3 +287,34 @@ def mad(a: np.ndarray, region=None):
     else:
         d = np.abs(vals.astype(np.int32) - np.int32(m))
     return float(m), float(np.partition(d, k)[k]), n
+
+
+def minimap_cells(dims, cell):
+    """Boxes (x0,y0,z0,x1,y1,z1) of the mini-map cells, x-fastest cell order."""
+    nx, ny, nz = dims
+    cx, cy, cz = cell
+    if min(cx, cy, cz) < 1:
+        raise ValueError("cell edges must be >= 1")
+    out = []
+    for z0 in range(0, nz, cz):
+        for y0 in range(0, ny, cy):
+            for x0 in range(0, nx, cx):
+                out.append((x0, y0, z0, min(x0 + cx, nx), min(y0 + cy, ny), min(z0 + cz, nz)))
+    return np.array(out, dtype=np.int64).reshape(-1, 6)
+
+
+def sigma_counts(a: np.ndarray, cell, k: float) -> np.ndarray:
+    """Per mini-map cell: the number of non-NaN voxels x with x > mean + k*std
+    (the cell's own moments, double precision; the comparison is made in double
+    on the exactly converted value).  Cells without a valid voxel count 0."""
+    nz, ny, nx = a.shape
+    boxes = minimap_cells((nx, ny, nz), cell)
+    out = np.zeros(len(boxes), dtype=np.uint64)
+    for i, b in enumerate(boxes):
+        mo = moments(a, b)
+        if mo["count"] == 0:
+            continue
+        thr = mo["mean"] + k * mo["std"]
+        v = _region_view(a, b).astype(np.float64)
+        out[i] = np.count_nonzero(v > thr)  # NaN compares false
+    return out
