@@ -27,7 +27,10 @@ slow restatement of what the paper (arXiv 1211.4896) defines:
                -- Section 4.5's statistical mini-map: the cube cut into cells
                   of cx*cy*cz voxels (the last cell along an axis keeps the
                   remainder), each summarised by its statistics, and the local
-                  threshold: per cell, the voxels above mean + k * std.
+                  threshold: per cell, the voxels above mean + k * std;
+* spectrum     -- Section 4.4's 3-D spectrum tool: the cube sampled along
+                  arbitrary rays at a constant step, each sample a trilinear
+                  interpolation of its eight neighbouring voxels (Fig. 8).
 
 NaN is the NULL value and is excluded everywhere.  The C parts live in
 tsa_oracle.c and are built with gcc by ``build()``.
@@ -317,4 +320,63 @@ def sigma_counts(a: np.ndarray, cell, k: float) -> np.ndarray:
         thr = mo["mean"] + k * mo["std"]
         v = _region_view(a, b).astype(np.float64)
         out[i] = np.count_nonzero(v > thr)  # NaN compares false
+    return out
+
+
+def _axis_cell(p: np.ndarray, n: int):
+    """Lower corner index, fraction and upper corner index of coordinates p
+    (all inside [0, n-1]) along an axis of n voxels."""
+    i0 = np.floor(p).astype(np.int64)
+    if n >= 2:
+        i0 = np.minimum(i0, n - 2)
+    else:
+        i0 = np.zeros_like(i0)
+    f = p - i0
+    i1 = np.minimum(i0 + 1, n - 1)
+    return i0, f, i1
+
+
+def spectrum(a: np.ndarray, origins, steps, nsamples: int) -> np.ndarray:
+    """Section 4.4 (with Fig. 8): a data profile along a ray through the cube,
+    sampled at a constant step and trilinearly interpolated.
+
+    Voxel (x, y, z) = a[z, y, x] sits at the integer point (x, y, z).  Ray r's
+    sample i is at p = origin[r] + i * step[r], per coordinate: i * step
+    rounded to double, then added to the origin and rounded.  A sample outside
+    [0, nx-1] x [0, ny-1] x [0, nz-1] is NaN.  Inside, per axis
+    x0 = min(floor(x), nx - 2) (0 when nx == 1), fx = x - x0,
+    x1 = min(x0 + 1, nx - 1), and the same for y and z.  Corner c = bx + 2 by
+    + 4 bz takes (x_bx, y_by, z_bz) with weight (wx * wy) * wz, where w is
+    1 - f for bit 0 and f for bit 1.  The sample is 0.0 plus weight * value
+    for c = 0, 1, ..., 7 in that order, corners of weight 0 skipped, all in
+    double; a NaN corner of non-zero weight makes it NaN.
+    Returns float64 [nrays, nsamples]."""
+    a = np.asarray(a)
+    nz, ny, nx = a.shape
+    o = np.asarray(origins, dtype=np.float64).reshape(-1, 3)
+    s = np.asarray(steps, dtype=np.float64).reshape(-1, 3)
+    if nsamples < 0 or len(o) != len(s):
+        raise ValueError("bad rays")
+    out = np.full((len(o), nsamples), np.nan)
+    ii = np.arange(nsamples, dtype=np.float64)
+    for r in range(len(o)):
+        px = o[r, 0] + ii * s[r, 0]
+        py = o[r, 1] + ii * s[r, 1]
+        pz = o[r, 2] + ii * s[r, 2]
+        inside = (px >= 0) & (px <= nx - 1) & (py >= 0) & (py <= ny - 1) & (pz >= 0) & (pz <= nz - 1)
+        if not inside.any():
+            continue
+        x0, fx, x1 = _axis_cell(px[inside], nx)
+        y0, fy, y1 = _axis_cell(py[inside], ny)
+        z0, fz, z1 = _axis_cell(pz[inside], nz)
+        xs, ys, zs = (x0, x1), (y0, y1), (z0, z1)
+        wx, wy, wz = (1.0 - fx, fx), (1.0 - fy, fy), (1.0 - fz, fz)
+        acc = np.zeros(len(x0))
+        for c in range(8):
+            bx, by, bz = c & 1, (c >> 1) & 1, (c >> 2) & 1
+            w = (wx[bx] * wy[by]) * wz[bz]
+            v = a[zs[bz], ys[by], xs[bx]].astype(np.float64)
+            used = w != 0.0
+            acc[used] = acc[used] + w[used] * v[used]
+        out[r, inside] = acc
     return out
