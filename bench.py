@@ -111,6 +111,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run (c5)")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-qps", type=float, default=2000.0)
+    ap.add_argument("--no-minimap", action="store_true", help="skip the mini-map + k-sigma measurement")
+    ap.add_argument("--no-spectrum", action="store_true", help="skip the spectrum-tool measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this path does not shard)",
@@ -200,6 +202,10 @@ def main():
         line["ops"] = _separate_ops(tsa, api, dev, cp, N, float(res["min"]), float(res["max"]), nbins, sh)
     if args.calib_copy:
         line["calib_copy_bytes"] = _calib_copy(lib, dev.device, sh)
+    if not args.no_minimap:
+        line["minimap"] = _minimap_bench(tsa, torch, api, lib, dev, sh, args.region_reps)
+    if not args.no_spectrum:
+        line["spectrum"] = _spectrum_bench(tsa, torch, np, api, lib, dev, sh, args.region_reps)
     del dev, ws
     torch.cuda.empty_cache()
     if not args.no_region:
@@ -321,6 +327,119 @@ def _region_batch_bench(tsa, torch, np, synth, reps: int) -> dict:
                                                           "blocks_per_cu": best[2], "cand_max": best[3],
                                                           "tuner_best_ms": round(best_ms, 3),
                                                           "tuning_s": round(t_tune, 1)}}
+
+
+def _minimap_bench(tsa, torch, api, lib, dev, sh, reps: int) -> dict:
+    """The statistical mini-map of the resident cube: 30x30x30-voxel cells
+    (the partition size of the paper's sigma-clipping example), each with
+    moments + 64-bin histogram over its own [min,max] + median, then the
+    local 3-sigma counts."""
+    cell, nbins, k = (30, 30, 30), 64, 3.0
+    c = tsa.cube_of(dev)
+    cp = ctypes.byref(c)
+    ncells = int(api.tsa_minimap_cells(cp, *cell))
+    ws = torch.empty(api.tsa_minimap_workspace_bytes(cp, *cell, nbins), dtype=torch.uint8, device=dev.device)
+    cells = torch.empty(72 * ncells, dtype=torch.uint8, device=dev.device)
+    hists = torch.empty((ncells, nbins), dtype=torch.int64, device=dev.device)
+    above = torch.empty(ncells, dtype=torch.int64, device=dev.device)
+
+    def mm():
+        st = api.tsa_minimap(cp, *cell, nbins, cells.data_ptr(), hists.data_ptr(), ws.data_ptr(), ws.numel(), sh)
+        if st != 0:
+            raise RuntimeError(f"tsa_minimap: {tsa.status_string(st)}")
+
+    def sig():
+        st = api.tsa_sigma_count(cp, *cell, cells.data_ptr(), k, above.data_ptr(), sh)
+        if st != 0:
+            raise RuntimeError(f"tsa_sigma_count: {tsa.status_string(st)}")
+
+    mm()
+    sig()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        mm()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    mm_ms = e0.elapsed_time(e1) / reps
+    e0.record(stream)
+    for _ in range(reps):
+        sig()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    sig_ms = e0.elapsed_time(e1) / reps
+    _trace(lib, True, cap=reps * 16)
+    for _ in range(reps):
+        mm()
+        sig()
+    torch.cuda.synchronize()
+    kern = _trace_read(lib)
+    _trace(lib, False)
+    res = tsa.results_to_numpy(cells)
+    N = dev.numel()
+    ks = kern.get("sigma", [1, sig_ms, 0, 0])
+    sig_kernel_ms = ks[1] / ks[0]
+    sig_bytes = 4.0 * N + 8.0 * ncells
+    return {"workload": f"mini-map of the resident {c.nx}x{c.ny}x{c.nz} float32 cube: {ncells} cells of "
+                        f"30x30x30 voxels, moments + {nbins}-bin histogram over own [min,max] + median each; "
+                        f"then per-cell counts above mean + 3 std",
+            "cells": ncells, "minimap_ms": round(mm_ms, 3), "minimap_gvoxel_s": round(N / (mm_ms * 1e-3) / 1e9, 1),
+            "cells_per_s": round(ncells / (mm_ms * 1e-3), 1),
+            "sigma_ms": round(sig_ms, 4), "sigma_kernel_ms": round(sig_kernel_ms, 4),
+            "sigma_hbm_frac": round(sig_bytes / (sig_kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "kernels_ms": {kk: round(v[1] / v[0], 4) for kk, v in kern.items()},
+            "status_errors": int((res["status"] != 0).sum()), "above_total": int(above.sum().item())}
+
+
+def _spectrum_bench(tsa, torch, np, api, lib, dev, sh, reps: int) -> dict:
+    """The 3-D spectrum tool over the resident cube: 16384 lines of sight
+    entering through the z = 0 face at seeded random points, directions within
+    45 degrees of the frequency axis, 0.5-voxel steps, 2560 trilinear samples
+    each."""
+    nrays, nsamples, step = 16384, 2560, 0.5
+    c = tsa.cube_of(dev)
+    rng = np.random.default_rng(4404)
+    o = np.stack([rng.uniform(0, c.nx - 1, nrays), rng.uniform(0, c.ny - 1, nrays), np.zeros(nrays)], axis=1)
+    th = np.arccos(rng.uniform(np.cos(np.pi / 4), 1.0, nrays))
+    ph = rng.uniform(0, 2 * np.pi, nrays)
+    d = np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)], axis=1) * step
+    rays = torch.from_numpy(np.concatenate([o, d], axis=1)).to(dev.device)
+    out = torch.empty((nrays, nsamples), dtype=torch.float64, device=dev.device)
+
+    def run():
+        st = api.tsa_spectrum(ctypes.byref(c), rays.data_ptr(), nrays, nsamples, out.data_ptr(), sh)
+        if st != 0:
+            raise RuntimeError(f"tsa_spectrum: {tsa.status_string(st)}")
+
+    run()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    _trace(lib, True, cap=reps * 2)
+    for _ in range(reps):
+        run()
+    torch.cuda.synchronize()
+    kern = _trace_read(lib)
+    _trace(lib, False)
+    inside = int(torch.isfinite(out).sum().item())
+    ns = nrays * nsamples
+    kk = kern.get("spectrum", [1, ms, 0, 0])
+    kms = kk[1] / kk[0]
+    return {"workload": f"{nrays} rays x {nsamples} samples (0.5-voxel step, within 45 deg of the z axis, entering "
+                        f"at z = 0) through the resident {c.nx}x{c.ny}x{c.nz} float32 cube",
+            "samples": ns, "inside_samples": inside, "ms": round(ms, 3), "kernel_ms": round(kms, 4),
+            "gsamples_s": round(ns / (kms * 1e-3) / 1e9, 2),
+            "inside_gsamples_s": round(inside / (kms * 1e-3) / 1e9, 2),
+            "out_gb_s": round(8.0 * ns / (kms * 1e-3) / 1e9, 1),
+            "gathered_gb_s": round((32.0 * inside + 8.0 * ns) / (kms * 1e-3) / 1e9, 1)}
 
 
 def _serving_bench(torch, np, synth, seconds: float, qps: float) -> dict:

@@ -92,7 +92,9 @@ typedef enum {
   TSA_OP_HISTOGRAM = 1,
   TSA_OP_MEDIAN = 2,
   TSA_OP_STATS = 3,
-  TSA_OP_REGION_BATCH = 4
+  TSA_OP_REGION_BATCH = 4,
+  TSA_OP_QUANTILE = 5,
+  TSA_OP_MAD = 6
 } tsa_op;
 
 /* Tunables of tsa_region_batch (NULL = the library's tuned choice). */
@@ -160,6 +162,31 @@ int tsa_stats(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa
               tsa_stream_t stream);
 
 /*
+ * The lower q-quantile: the non-NaN value of 0-based rank floor(q * (count-1))
+ * under totalOrder, the product rounded to double (q in [0, 1]; q = 0.5 is the
+ * lower median).  The same radix selection as tsa_median.  digits = 3 selects
+ * every key bit (exact); digits = 1 or 2 stops after that many digits (one or
+ * two passes over the data; the median of Section 4.3's sample run is known
+ * to ~1e-6 after 20 of its 31 iterations, this is the radix analogue) and
+ * returns the smallest value of the key bucket holding the rank.
+ * d_out (device, 3 doubles) = (value, bucket width, count): the exact answer
+ * lies in [value, value + width]; width is 0 when digits = 3.  NaN, NaN, 0
+ * without a valid voxel.  TSA_EINVAL for q outside [0,1] or digits outside 1..3.
+ */
+int tsa_quantile(const tsa_cube* cube, const tsa_region* region, double q, int32_t digits, double* d_out,
+                 void* d_ws, size_t ws_bytes, tsa_stream_t stream);
+
+/*
+ * Median absolute deviation (Section 4.3 names it as an extension of the
+ * median method): m = the lower median, then the lower median of |x - m| over
+ * the non-NaN values, x - m rounded to single precision (int16: exact).
+ * Four radix passes over the data.  d_out (device, 3 doubles) = (m, MAD,
+ * count); NaN, NaN, 0 without a valid voxel.
+ */
+int tsa_mad(const tsa_cube* cube, const tsa_region* region, double* d_out, void* d_ws, size_t ws_bytes,
+            tsa_stream_t stream);
+
+/*
  * Batched region queries ("local" statistics over user-defined regions,
  * Section 4; the statistical mini-map of Section 4.5 is a regular grid of
  * them).  For each of the nq boxes in d_regions (device array), computes what
@@ -168,7 +195,8 @@ int tsa_stats(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa
  * uint64).  All queries run in one persistent kernel fed by a device work
  * queue of (query, phase, tile) items; no host round trip.  An invalid box
  * sets TSA_FLAG_BAD_REGION and status TSA_EINVAL in its own result only.
- * nq in [1, 1<<20], nbins in [1, 4096].  tune may be NULL.
+ * nq in [1, 65536], nbins in [1, 4096], each box below 2^32 voxels.  tune
+ * may be NULL.
  */
 int tsa_region_batch(const tsa_cube* cube, const tsa_region* d_regions, int32_t nq, int32_t nbins,
                      tsa_result* d_results, uint64_t* d_hists, const tsa_tune* tune, void* d_ws,
@@ -186,6 +214,63 @@ int tsa_region_batch(const tsa_cube* cube, const tsa_region* d_regions, int32_t 
 int tsa_tune_region_batch(const tsa_cube* cube, const tsa_region* d_regions, int32_t nq, int32_t nbins,
                           tsa_result* d_results, uint64_t* d_hists, void* d_ws, size_t ws_bytes,
                           tsa_stream_t stream, int32_t reps, tsa_tune* best, float* best_ms);
+
+/*
+ * Statistical mini-map (Section 4.5): the scaled-down cube whose points each
+ * summarise a larger region.  The cube is cut into cells of
+ * cell_x * cell_y * cell_z voxels, the last cell along an axis keeping the
+ * remainder; cell (i, j, k) covers [i cx, min((i+1) cx, nx)) x ... and is
+ * entry i + ncx (j + ncy k) of the outputs, with ncx = ceil(nx / cx) and so on.
+ * Each cell gets what tsa_region_batch gives a box: d_cells (device,
+ * ncells tsa_result) and d_hists (device, ncells * nbins uint64, each over the
+ * cell's own [min, max]).  The cell boxes are planned on the device and the
+ * statistics come from one region batch.  Workspace:
+ * tsa_minimap_workspace_bytes().  TSA_EINVAL for cell edges < 1, more than
+ * 65536 cells, a cell of 2^32 voxels or more, nbins outside [1, 4096].
+ */
+int tsa_minimap(const tsa_cube* cube, int32_t cell_x, int32_t cell_y, int32_t cell_z, int32_t nbins,
+                tsa_result* d_cells, uint64_t* d_hists, void* d_ws, size_t ws_bytes, tsa_stream_t stream);
+
+/* Workspace bytes of tsa_minimap (0 on bad arguments). */
+size_t tsa_minimap_workspace_bytes(const tsa_cube* cube, int32_t cell_x, int32_t cell_y, int32_t cell_z,
+                                   int32_t nbins);
+
+/* Number of mini-map cells for these cell edges, or a negative status. */
+int64_t tsa_minimap_cells(const tsa_cube* cube, int32_t cell_x, int32_t cell_y, int32_t cell_z);
+
+/*
+ * Local k-sigma threshold counts (Section 4.5: the mini-map's statistics set
+ * a local threshold): for every cell c, the number of non-NaN voxels v of c
+ * with v > mean_c + k * std_c, where mean_c and std_c are d_cells[c] as
+ * written by tsa_minimap for the same cube and cell edges, and the threshold
+ * is k * std_c rounded to double, then added to mean_c and rounded to double;
+ * v is compared exactly (int16 converted to float).  Cells without a valid
+ * voxel count 0.  d_above (device, ncells uint64) is overwritten.  One
+ * streaming pass over the cube; no workspace.  TSA_EINVAL for a non-finite k
+ * or bad cell edges (as tsa_minimap).
+ */
+int tsa_sigma_count(const tsa_cube* cube, int32_t cell_x, int32_t cell_y, int32_t cell_z,
+                    const tsa_result* d_cells, double k, uint64_t* d_above, tsa_stream_t stream);
+
+/*
+ * 3-D spectrum tool (Section 4.4, Fig. 8): data profiles along arbitrary
+ * rays, sampled at a constant step with trilinear interpolation.
+ * d_rays (device, nrays x 6 doubles) holds per ray its origin (ox, oy, oz)
+ * and step vector (sx, sy, sz) in voxel units, voxel (x, y, z) sitting at the
+ * integer point (x, y, z).  Sample i of ray r (0 <= i < nsamples) is at
+ * p = origin + i * step per coordinate (the product rounded to double, then
+ * the sum).  A sample outside [0, nx-1] x [0, ny-1] x [0, nz-1] is NaN.
+ * Inside, per axis x0 = min(floor(x), nx - 2) (0 when nx == 1),
+ * fx = x - x0, x1 = min(x0 + 1, nx - 1); corner c = bx + 2 by + 4 bz has
+ * weight (wx * wy) * wz with w = 1 - f for bit 0 and f for bit 1, and the
+ * sample is 0.0 plus weight * value over c = 0..7 in order, corners of weight
+ * 0 skipped, in double (int16 converted exactly); a NaN corner of non-zero
+ * weight gives NaN.  d_out (device, nrays x nsamples doubles, ray-major) is
+ * overwritten.  nrays or nsamples 0: nothing to do.  TSA_EINVAL for negative
+ * counts, null pointers, or more than 2^31 samples' worth of launch.
+ */
+int tsa_spectrum(const tsa_cube* cube, const double* d_rays, int32_t nrays, int32_t nsamples, double* d_out,
+                 tsa_stream_t stream);
 
 /* Write the remembered tuning choices as JSON to `path` (host file).  The
  * library also loads the file named by the environment variable

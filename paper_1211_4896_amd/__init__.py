@@ -32,7 +32,7 @@ LIB_PATH = os.environ.get("TSA_LIB") or os.path.join(_HERE, "libtsa.so")
 
 TSA_OK, TSA_EINVAL, TSA_ENOMEM, TSA_EDEVICE, TSA_ENOTSUP, TSA_EBUSY = 0, -1, -2, -3, -4, -5
 TSA_F32, TSA_I16 = 0, 1
-OP_MOMENTS, OP_HISTOGRAM, OP_MEDIAN, OP_STATS, OP_REGION_BATCH = 0, 1, 2, 3, 4
+OP_MOMENTS, OP_HISTOGRAM, OP_MEDIAN, OP_STATS, OP_REGION_BATCH, OP_QUANTILE, OP_MAD = 0, 1, 2, 3, 4, 5, 6
 FLAG_HIST_SKIPPED, FLAG_BAD_REGION, FLAG_PHASE3 = 1, 2, 4
 
 
@@ -86,7 +86,14 @@ class _CAPI:
             "tsa_tune_region_batch": (ctypes.c_int, [CP, P, I32, I32, P, P, P, SZ, P, I32, ctypes.POINTER(Tune),
                                                      ctypes.POINTER(ctypes.c_float)]),
             "tsa_tune_save": (ctypes.c_int, [ctypes.c_char_p]),
+            "tsa_quantile": (ctypes.c_int, [CP, RP, ctypes.c_double, I32, P, P, SZ, P]),
+            "tsa_mad": (ctypes.c_int, [CP, RP, P, P, SZ, P]),
             "tsa_tune_load": (ctypes.c_int, [ctypes.c_char_p]),
+            "tsa_minimap_workspace_bytes": (SZ, [CP, I32, I32, I32, I32]),
+            "tsa_minimap_cells": (I64, [CP, I32, I32, I32]),
+            "tsa_minimap": (ctypes.c_int, [CP, I32, I32, I32, I32, P, P, P, SZ, P]),
+            "tsa_sigma_count": (ctypes.c_int, [CP, I32, I32, I32, P, ctypes.c_double, P, P]),
+            "tsa_spectrum": (ctypes.c_int, [CP, P, I32, I32, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -245,6 +252,33 @@ def stats(t, nbins: int, region=None, stream=None):
     return _rec(results_to_numpy(out)[0]), counts, outl
 
 
+def quantile(t, q: float, region=None, digits: int = 3, stream=None):
+    """Lower q-quantile (rank floor(q (n-1))).  Returns (value, width, count):
+    the exact value lies in [value, value + width] (width 0 when digits = 3)."""
+    torch = _torch()
+    c, reg = cube_of(t), region_of(region)
+    ws = workspace(OP_QUANTILE, t, region)
+    out = torch.empty(3, dtype=torch.float64, device=t.device)
+    _check(capi().tsa_quantile(ctypes.byref(c), _rp(reg), q, digits, out.data_ptr(), ws.data_ptr(), ws.numel(),
+                               _stream(stream)), "tsa_quantile")
+    torch.cuda.synchronize(t.device)
+    v = out.cpu().tolist()
+    return v[0], v[1], int(v[2])
+
+
+def mad(t, region=None, stream=None):
+    """Median absolute deviation.  Returns (median, mad, count)."""
+    torch = _torch()
+    c, reg = cube_of(t), region_of(region)
+    ws = workspace(OP_MAD, t, region)
+    out = torch.empty(3, dtype=torch.float64, device=t.device)
+    _check(capi().tsa_mad(ctypes.byref(c), _rp(reg), out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream)),
+           "tsa_mad")
+    torch.cuda.synchronize(t.device)
+    v = out.cpu().tolist()
+    return v[0], v[1], int(v[2])
+
+
 def region_batch(t, regions, nbins: int, tune: Optional[Sequence[int]] = None, stream=None, ws=None):
     """Batched region queries.  regions: int64 [nq, 6] (host or device).
 
@@ -281,6 +315,57 @@ def tune_region_batch(t, regions, nbins: int, reps: int = 3, stream=None):
                                         ws.data_ptr(), ws.numel(), _stream(stream), reps, ctypes.byref(best),
                                         ctypes.byref(ms)), "tsa_tune_region_batch")
     return (best.tile_voxels, best.block_threads, best.blocks_per_cu, best.cand_max), ms.value
+
+
+def minimap(t, cell: Sequence[int], nbins: int, stream=None, ws=None):
+    """Statistical mini-map: cells of cell = (cx, cy, cz) voxels, x fastest.
+
+    Returns (numpy record array of the cells' results, hists int64 tensor
+    [ncells, nbins], the device result buffer for sigma_count)."""
+    torch = _torch()
+    c = cube_of(t)
+    cx, cy, cz = (int(v) for v in cell)
+    ncells = capi().tsa_minimap_cells(ctypes.byref(c), cx, cy, cz)
+    _check(int(ncells) if ncells < 0 else TSA_OK, "tsa_minimap_cells")
+    if ws is None:
+        nb = capi().tsa_minimap_workspace_bytes(ctypes.byref(c), cx, cy, cz, nbins)
+        if nb == 0:
+            raise TsaError(TSA_EINVAL, "tsa_minimap_workspace_bytes")
+        ws = torch.empty(nb, dtype=torch.uint8, device=t.device)
+    out = torch.empty(72 * ncells, dtype=torch.uint8, device=t.device)
+    hists = torch.empty((ncells, nbins), dtype=torch.int64, device=t.device)
+    _check(capi().tsa_minimap(ctypes.byref(c), cx, cy, cz, nbins, out.data_ptr(), hists.data_ptr(), ws.data_ptr(),
+                              ws.numel(), _stream(stream)), "tsa_minimap")
+    torch.cuda.synchronize(t.device)
+    return results_to_numpy(out), hists, out
+
+
+def sigma_count(t, cell: Sequence[int], cells_dev, k: float, stream=None):
+    """Per mini-map cell, the voxels above its mean + k*std; cells_dev is the
+    device result buffer that minimap returned.  Returns a uint64 numpy array."""
+    torch = _torch()
+    c = cube_of(t)
+    cx, cy, cz = (int(v) for v in cell)
+    ncells = capi().tsa_minimap_cells(ctypes.byref(c), cx, cy, cz)
+    _check(int(ncells) if ncells < 0 else TSA_OK, "tsa_minimap_cells")
+    above = torch.empty(ncells, dtype=torch.int64, device=t.device)
+    _check(capi().tsa_sigma_count(ctypes.byref(c), cx, cy, cz, cells_dev.data_ptr(), float(k), above.data_ptr(),
+                                  _stream(stream)), "tsa_sigma_count")
+    torch.cuda.synchronize(t.device)
+    return above.cpu().numpy().view(np.uint64)
+
+
+def spectrum(t, rays, nsamples: int, stream=None):
+    """Trilinear samples along rays.  rays: float64 [nrays, 6] = origin (x, y, z)
+    and step (x, y, z) in voxel units.  Returns a float64 tensor [nrays, nsamples]."""
+    torch = _torch()
+    c = cube_of(t)
+    r = torch.as_tensor(rays, dtype=torch.float64).reshape(-1, 6).to(t.device).contiguous()
+    out = torch.empty((r.shape[0], nsamples), dtype=torch.float64, device=t.device)
+    _check(capi().tsa_spectrum(ctypes.byref(c), r.data_ptr(), r.shape[0], nsamples, out.data_ptr(), _stream(stream)),
+           "tsa_spectrum")
+    torch.cuda.synchronize(t.device)
+    return out
 
 
 def version() -> str:

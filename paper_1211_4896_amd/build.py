@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtsa.so")
 
-SOURCES = ["tsa_kernels.hip", "tsa_hist_wide.hip", "tsa_batch.hip", "tsa_serve.hip", "tsa_tune.hip", "tsa_trace.hip", "tsa_api.hip"]
+SOURCES = ["tsa_kernels.hip", "tsa_hist_wide.hip", "tsa_batch.hip", "tsa_serve.hip", "tsa_tune.hip", "tsa_minimap.hip", "tsa_spectrum.hip", "tsa_trace.hip", "tsa_api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

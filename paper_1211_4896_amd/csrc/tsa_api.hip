@@ -18,7 +18,7 @@ size_t tsa_workspace_bytes(int32_t op, const tsa_cube* cube, const tsa_region* r
     if (nq < 1 || nq > (1 << 20) || nbins < 1 || nbins > 4096) return 0;
     return batch_ws_bytes(cube, nbins, nq);
   }
-  if (op < TSA_OP_MOMENTS || op > TSA_OP_STATS) return 0;
+  if (op < TSA_OP_MOMENTS || op > TSA_OP_MAD || op == TSA_OP_REGION_BATCH) return 0;
   if ((op == TSA_OP_HISTOGRAM || op == TSA_OP_STATS) && (nbins < 1 || nbins > 65536)) return 0;
   tsa_region b;
   if (region_box(cube, region, &b) != TSA_OK) return 0;
@@ -44,6 +44,16 @@ int tsa_median(const tsa_cube* cube, const tsa_region* region, tsa_result* d_out
 int tsa_stats(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa_result* d_out, uint64_t* d_counts,
               uint64_t* d_outliers, void* d_ws, size_t ws_bytes, tsa_stream_t stream) {
   return run_stats(cube, region, nbins, d_out, d_counts, d_outliers, d_ws, ws_bytes, stream);
+}
+
+int tsa_quantile(const tsa_cube* cube, const tsa_region* region, double q, int32_t digits, double* d_out,
+                 void* d_ws, size_t ws_bytes, tsa_stream_t stream) {
+  return run_quantile(cube, region, q, digits, d_out, d_ws, ws_bytes, stream);
+}
+
+int tsa_mad(const tsa_cube* cube, const tsa_region* region, double* d_out, void* d_ws, size_t ws_bytes,
+            tsa_stream_t stream) {
+  return run_mad(cube, region, d_out, d_ws, ws_bytes, stream);
 }
 
 int tsa_region_batch(const tsa_cube* cube, const tsa_region* d_regions, int32_t nq, int32_t nbins,

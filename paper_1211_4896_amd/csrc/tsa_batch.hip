@@ -623,11 +623,15 @@ __global__ __launch_bounds__(kBBlock) void k_batch(BArgs a) {
       if (!block_wait_ge(&a.hdr->p2_done, (uint32_t)a.nq, &a.hdr->err, sh)) return;
       if (__hip_atomic_load(&a.hdr->any3, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0 || lt >= T1) return;
     }
-    // ticket -> (query, tile)
+    // ticket -> (query, tile).  Tiles are visited in the order of the
+    // bijection lt -> lt * (2^31 - 1) mod T1 (the multiplier is prime and
+    // exceeds T1), so blocks running at the same time work on different boxes
+    // instead of all adding into one box's counters.
     if (t == 0) {
-      const uint32_t qq = a.tile_q[lt];
+      const uint64_t pt = (lt * 2147483647ull) % T1;
+      const uint32_t qq = a.tile_q[pt];
       sh.q = qq;
-      sh.tile = (uint32_t)(lt - a.tile_base[qq]);
+      sh.tile = (uint32_t)(pt - a.tile_base[qq]);
     }
     __syncthreads();
     const uint32_t q = sh.q, tile = sh.tile;

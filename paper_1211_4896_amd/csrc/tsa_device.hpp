@@ -169,7 +169,10 @@ struct SelState {
   float shift;        // fused path: fl32(mean) that pass B subtracts before squaring
   uint32_t var_on;    // fused path: pass B recomputes M2 about `shift`
   int32_t vscale;     // fused path: deviations are scaled by 2^vscale before squaring
+  double q;           // rank_mode 1: the rank is floor(q (n - 1))
+  uint32_t rank_mode; // 0: lower median, 1: quantile q
+  uint32_t levels;    // digits to select before stopping (3 = exact)
 };
-static_assert(sizeof(SelState) == 80, "state layout");
+static_assert(sizeof(SelState) == 96, "state layout");
 
 }  // namespace tsa

@@ -57,6 +57,10 @@ int run_histogram_wide(const tsa_cube* cube, const Geom& g, bool vec, int grid, 
                        float scale, int32_t nbins, uint64_t* d_counts, uint64_t* d_outl, hipStream_t s);
 int run_median(const tsa_cube* cube, const tsa_region* region, tsa_result* d_out, void* d_ws, size_t ws_bytes,
                tsa_stream_t stream);
+int run_quantile(const tsa_cube* cube, const tsa_region* region, double q, int32_t digits, double* d_out,
+                 void* d_ws, size_t ws_bytes, tsa_stream_t stream);
+int run_mad(const tsa_cube* cube, const tsa_region* region, double* d_out, void* d_ws, size_t ws_bytes,
+            tsa_stream_t stream);
 int run_stats(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa_result* d_out, uint64_t* d_counts,
               uint64_t* d_outliers, void* d_ws, size_t ws_bytes, tsa_stream_t stream);
 

@@ -231,8 +231,11 @@ struct SelectShared {
 // Level 1 also fixes n and the rank k = floor((n-1)/2) of the lower median.
 // When the key is complete, writes the median (and, if write_counts, the
 // count fields) to *out.
+// With qout != NULL the finished selection goes to qout[0..2] = (value, width of
+// the bucket it came from (0 when all digits were selected), count) instead of
+// out->median.  st->rank_mode / q / levels select the rank and an early stop.
 TSA_DEV void select_level(int level, const uint64_t* __restrict__ hist, SelState* st, int dtype, uint64_t volume,
-                          tsa_result* out, bool write_counts, SelectShared& sm) {
+                          tsa_result* out, bool write_counts, SelectShared& sm, double* qout = nullptr) {
   if (st->done) return;
   const int nb = level == 3 ? kBins3 : kBins1;
   const int shift = level == 1 ? kShift1 : level == 2 ? kShift2 : 0;
@@ -264,6 +267,10 @@ TSA_DEV void select_level(int level, const uint64_t* __restrict__ hist, SelState
     if (t == 0) {
       st->n = 0;
       st->done = 1;
+      if (qout) {
+        qout[0] = qout[1] = __builtin_nan("");
+        qout[2] = 0.0;
+      }
       out->median = __builtin_nan("");
       if (write_counts) {
         out->count = 0;
@@ -273,7 +280,15 @@ TSA_DEV void select_level(int level, const uint64_t* __restrict__ hist, SelState
     }
     return;
   }
-  const uint64_t k = level == 1 ? (n - 1) / 2 : st->k;
+  uint64_t k = st->k;
+  if (level == 1) {
+    if (st->rank_mode) {
+      const double kk = floor(st->q * (double)(n - 1));
+      k = kk <= 0.0 ? 0 : kk >= (double)(n - 1) ? n - 1 : (uint64_t)kk;
+    } else {
+      k = (n - 1) / 2;
+    }
+  }
   __syncthreads();  // every thread has read st before it changes
   if (local > 0 && k >= base && k < base + local) {
     uint64_t cum = base;
@@ -294,10 +309,23 @@ TSA_DEV void select_level(int level, const uint64_t* __restrict__ hist, SelState
     st->prefix = prefix;
     st->level = level;
     if (level == 1) st->compact = bucket <= st->cand_cap ? 1u : 0u;
-    const bool complete = level == 3 || (dtype == 1 && level == 2);
+    const bool exact = level == 3 || (dtype == 1 && level == 2);
+    const bool complete = exact || (st->levels >= 1 && (uint32_t)level >= st->levels);
     if (complete) {
       st->done = 1;
       st->result_key = prefix;
+      if (qout) {
+        // the bucket [prefix, prefix | rest] holds the rank: its smallest value
+        // and its width bound the early answer
+        uint32_t rest = level == 1 ? 0x000FFFFFu : level == 2 ? 0xFFu : 0u;
+        if (dtype == 1) rest &= 0xFFFF0000u;
+        double lo = value_of_key(prefix, dtype), hi = value_of_key(prefix | rest, dtype);
+        if (lo != lo) lo = -__builtin_inf();
+        if (hi != hi) hi = __builtin_inf();
+        qout[0] = lo;
+        qout[1] = exact ? 0.0 : hi - lo;
+        qout[2] = (double)n;
+      }
       out->median = value_of_key(prefix, dtype);
       if (write_counts) {
         out->count = n;
@@ -316,9 +344,96 @@ TSA_DEV void select_level(int level, const uint64_t* __restrict__ hist, SelState
 }
 
 __global__ __launch_bounds__(1024) void k_select(int level, const uint64_t* __restrict__ hist, SelState* st,
-                                                 int dtype, uint64_t volume, tsa_result* out, int write_counts) {
+                                                 int dtype, uint64_t volume, tsa_result* out, int write_counts,
+                                                 double* qout) {
   __shared__ SelectShared sm;
-  select_level(level, hist, st, dtype, volume, out, write_counts != 0, sm);
+  select_level(level, hist, st, dtype, volume, out, write_counts != 0, sm, qout);
+}
+
+// ---------------------------------------------------------------------------
+// median absolute deviation: the radix passes over d = |x - m|
+// ---------------------------------------------------------------------------
+template <int DT>
+TSA_DEV void median_of_state(const SelState* med, float& mf, int32_t& mi) {
+  const uint32_t k = med->result_key;
+  mf = __uint_as_float(f32bits_of_key(k));
+  mi = i16_of_key(k);
+}
+
+template <int DT, bool VEC, bool NT>
+__global__ __launch_bounds__(1024) void k_mlevel1(Geom g, uint32_t rshift, const SelState* __restrict__ med,
+                                                  uint64_t* __restrict__ hist1) {
+  extern __shared__ uint32_t lds[];
+  if (!med->done || med->n == 0) return;
+  lds_zero(lds, ((uint32_t)kBins1 << rshift) + kTrash);
+  __syncthreads();
+  float mf;
+  int32_t mi;
+  median_of_state<DT>(med, mf, mi);
+  AbsDev<DT, Digit1Acc<0>> a{Digit1Acc<0>{lds, rshift, threadIdx.x & ((1u << rshift) - 1u)}, mf, mi};
+  walk<DT, VEC, kUnroll, NT>(g, a);
+  __syncthreads();
+  lds_flush(lds, kBins1, rshift, hist1);
+}
+
+template <int DT, bool VEC, bool NT>
+__global__ __launch_bounds__(1024) void k_mlevel2(Geom g, const SelState* __restrict__ med, SelState* __restrict__ st,
+                                                  uint64_t* __restrict__ hist2, uint32_t* __restrict__ cand) {
+  __shared__ uint32_t lds[kBins2];
+  __shared__ CandShared cs;
+  if (st->done) return;
+  lds_zero(lds, kBins2);
+  cand_init(cs);
+  __syncthreads();
+  float mf;
+  int32_t mi;
+  median_of_state<DT>(med, mf, mi);
+  AbsDev<DT, Level2Acc<0>> a{
+      Level2Acc<0>{lds, st->prefix >> kShift1, st->compact != 0, CandSink{&cs, cand, &st->ncand, st->cand_cap}}, mf,
+      mi};
+  walk<DT, VEC, kUnroll, NT>(g, a);
+  a.inner.finish();
+  __syncthreads();
+  lds_flush(lds, kBins2, 0, hist2);
+}
+
+template <int DT, bool VEC, bool NT>
+__global__ __launch_bounds__(1024) void k_mlevel3(Geom g, const SelState* __restrict__ med, SelState* __restrict__ st,
+                                                  uint64_t* __restrict__ hist3, const uint32_t* __restrict__ cand) {
+  __shared__ uint32_t lds[kBins3];
+  if (st->done) return;
+  lds_zero(lds, kBins3);
+  __syncthreads();
+  const uint32_t p2 = st->prefix >> kShift2;
+  if (st->compact) {
+    const uint32_t n = min(st->ncand, st->cand_cap);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+      const uint32_t key = cand[i];
+      if ((key >> kShift2) == p2) lds_inc(lds, key & 0xFFu);
+    }
+  } else {
+    float mf;
+    int32_t mi;
+    median_of_state<DT>(med, mf, mi);
+    AbsDev<DT, Level3Acc<0>> a{Level3Acc<0>{lds, p2}, mf, mi};
+    walk<DT, VEC, kUnroll, NT>(g, a);
+  }
+  __syncthreads();
+  lds_flush(lds, kBins3, 0, hist3);
+}
+
+// out[0..2] = (median, MAD, count); NaN, NaN, 0 without a valid voxel.
+__global__ void k_mad_finish(const SelState* __restrict__ med, const SelState* __restrict__ st, int dtype,
+                             double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (med->n == 0 || !med->done || !st->done) {
+    out[0] = out[1] = __builtin_nan("");
+    out[2] = (double)med->n;
+    return;
+  }
+  out[0] = value_of_key(med->result_key, dtype);
+  out[1] = (double)__uint_as_float(f32bits_of_key(st->result_key));
+  out[2] = (double)med->n;
 }
 
 // ---------------------------------------------------------------------------
@@ -675,7 +790,7 @@ static int pass_grid(const Geom& g, bool vec, int block, int maxblocks) {
 
 // Workspace layout of the single-region calls.
 struct WsLayout {
-  size_t partials, partials2, hist1, hist2, hist3, state, outl, cand, total;
+  size_t partials, partials2, hist1, hist2, hist3, state, state2, result, outl, cand, total;
   uint32_t cand_cap;
 };
 
@@ -696,6 +811,10 @@ static WsLayout ws_layout(int64_t volume) {
   o = align256(o + 8 * kBins3);
   L.state = o;
   o = align256(o + sizeof(SelState));
+  L.state2 = o;
+  o = align256(o + sizeof(SelState));
+  L.result = o;
+  o = align256(o + sizeof(tsa_result));
   L.outl = o;
   o = align256(o + 16);
   int64_t cap = volume / 64;
@@ -860,21 +979,22 @@ int run_histogram(const tsa_cube* cube, const tsa_region* region, float lo, floa
   return run_histogram_wide(cube, P.g, P.vec, P.grid, P.block, lo, hi, scale, nbins, d_counts, outl, P.s);
 }
 
-static int launch_median_tail(const tsa_cube* cube, const Prep& P, tsa_result* d_out, bool write_counts) {
+static int launch_median_tail(const tsa_cube* cube, const Prep& P, tsa_result* d_out, bool write_counts,
+                              double* qout = nullptr) {
   SelState* stp = (SelState*)(P.ws + P.L.state);
   uint64_t* h2 = (uint64_t*)(P.ws + P.L.hist2);
   uint64_t* h3 = (uint64_t*)(P.ws + P.L.hist3);
   uint32_t* cand = (uint32_t*)(P.ws + P.L.cand);
   TSA_TRACED("select", P.s,
              hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, P.s, 2, (const uint64_t*)h2, stp, cube->dtype,
-                                (uint64_t)P.volume, d_out, (int)write_counts));
+                                (uint64_t)P.volume, d_out, (int)write_counts, qout));
   TSA_TRACED("level3", P.s,
     TSA_DISPATCH(cube->dtype, P.vec, tuning().nt,
                  hipLaunchKernelGGL((k_level3<DT, VEC, NT>), dim3(P.grid), dim3(P.block), 0, P.s, P.g, stp, h3,
                                     (const uint32_t*)cand)));
   TSA_TRACED("select", P.s,
              hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, P.s, 3, (const uint64_t*)h3, stp, cube->dtype,
-                                (uint64_t)P.volume, d_out, (int)write_counts));
+                                (uint64_t)P.volume, d_out, (int)write_counts, qout));
   return launch_ok();
 }
 
@@ -896,7 +1016,7 @@ int run_median(const tsa_cube* cube, const tsa_region* region, tsa_result* d_out
                                     P.s, P.g, rs, h1)));
   TSA_TRACED("select", P.s,
              hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, P.s, 1, (const uint64_t*)h1, stp, cube->dtype,
-                                (uint64_t)P.volume, d_out, 1));
+                                (uint64_t)P.volume, d_out, 1, (double*)nullptr));
   TSA_TRACED("level2", P.s,
     TSA_DISPATCH(cube->dtype, P.vec, tuning().nt,
                  hipLaunchKernelGGL((k_level2<DT, VEC, NT>), dim3(P.grid), dim3(P.block), 0, P.s, P.g, stp, h2, cand)));
@@ -960,6 +1080,103 @@ int run_stats(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa
              hipLaunchKernelGGL(k_var_finish, dim3(1), dim3(1024), 0, P.s, (const Partial*)parts2, np2,
                                 (const SelState*)stp, d_out));
   return launch_median_tail(cube, P, d_out, false);
+}
+
+
+__global__ void k_init_rank(SelState* st, double q, uint32_t mode, uint32_t levels) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->q = q;
+    st->rank_mode = mode;
+    st->levels = levels;
+  }
+}
+
+int run_quantile(const tsa_cube* cube, const tsa_region* region, double q, int32_t digits, double* d_out,
+                 void* d_ws, size_t ws_bytes, tsa_stream_t stream) {
+  if (!d_out || !(q >= 0.0 && q <= 1.0) || digits < 1 || digits > 3) return TSA_EINVAL;
+  Prep P;
+  int st = prepare(cube, region, d_ws, ws_bytes, stream, &P);
+  if (st) return st;
+  reset_select(P);
+  SelState* stp = (SelState*)(P.ws + P.L.state);
+  tsa_result* scratch = (tsa_result*)(P.ws + P.L.result);
+  uint64_t* h1 = (uint64_t*)(P.ws + P.L.hist1);
+  uint64_t* h2 = (uint64_t*)(P.ws + P.L.hist2);
+  uint32_t* cand = (uint32_t*)(P.ws + P.L.cand);
+  TSA_TRACED("init", P.s, hipLaunchKernelGGL(k_init_rank, dim3(1), dim3(64), 0, P.s, stp, q, 1u, (uint32_t)digits));
+  const uint32_t rs = rep_shift_for(kBins1, 32768);
+  TSA_TRACED("level1", P.s,
+    TSA_DISPATCH(cube->dtype, P.vec, tuning().nt,
+                 hipLaunchKernelGGL((k_level1<DT, VEC, NT>), dim3(P.grid), dim3(P.block),
+                                    (((size_t)kBins1 << rs) + kTrash) * 4, P.s, P.g, rs, h1)));
+  TSA_TRACED("select", P.s,
+             hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, P.s, 1, (const uint64_t*)h1, stp, cube->dtype,
+                                (uint64_t)P.volume, scratch, 0, d_out));
+  TSA_TRACED("level2", P.s,
+    TSA_DISPATCH(cube->dtype, P.vec, tuning().nt,
+                 hipLaunchKernelGGL((k_level2<DT, VEC, NT>), dim3(P.grid), dim3(P.block), 0, P.s, P.g, stp, h2,
+                                    cand)));
+  return launch_median_tail(cube, P, scratch, false, d_out);
+}
+
+int run_mad(const tsa_cube* cube, const tsa_region* region, double* d_out, void* d_ws, size_t ws_bytes,
+            tsa_stream_t stream) {
+  if (!d_out) return TSA_EINVAL;
+  Prep P;
+  int st = prepare(cube, region, d_ws, ws_bytes, stream, &P);
+  if (st) return st;
+  reset_select(P);
+  SelState* med = (SelState*)(P.ws + P.L.state);
+  SelState* sb = (SelState*)(P.ws + P.L.state2);
+  tsa_result* scratch = (tsa_result*)(P.ws + P.L.result);
+  uint64_t* h1 = (uint64_t*)(P.ws + P.L.hist1);
+  uint64_t* h2 = (uint64_t*)(P.ws + P.L.hist2);
+  uint64_t* h3 = (uint64_t*)(P.ws + P.L.hist3);
+  uint32_t* cand = (uint32_t*)(P.ws + P.L.cand);
+  fill32(sb, sizeof(SelState) / 4, 0u, P.s);
+  fill32((char*)sb + offsetof(SelState, cand_cap), 1, P.L.cand_cap, P.s);
+  // 1. the lower median m
+  const uint32_t rs = rep_shift_for(kBins1, 32768);
+  TSA_TRACED("level1", P.s,
+    TSA_DISPATCH(cube->dtype, P.vec, tuning().nt,
+                 hipLaunchKernelGGL((k_level1<DT, VEC, NT>), dim3(P.grid), dim3(P.block),
+                                    (((size_t)kBins1 << rs) + kTrash) * 4, P.s, P.g, rs, h1)));
+  TSA_TRACED("select", P.s,
+             hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, P.s, 1, (const uint64_t*)h1, med, cube->dtype,
+                                (uint64_t)P.volume, scratch, 0, (double*)nullptr));
+  TSA_TRACED("level2", P.s,
+    TSA_DISPATCH(cube->dtype, P.vec, tuning().nt,
+                 hipLaunchKernelGGL((k_level2<DT, VEC, NT>), dim3(P.grid), dim3(P.block), 0, P.s, P.g, med, h2,
+                                    cand)));
+  st = launch_median_tail(cube, P, scratch, false);
+  if (st) return st;
+  // 2. the lower median of |x - m| (float keys whatever the cube's type)
+  fill32(h1, (P.L.state - P.L.hist1) / 4, 0u, P.s);
+  TSA_TRACED("mad_level1", P.s,
+    TSA_DISPATCH(cube->dtype, P.vec, tuning().nt,
+                 hipLaunchKernelGGL((k_mlevel1<DT, VEC, NT>), dim3(P.grid), dim3(P.block),
+                                    (((size_t)kBins1 << rs) + kTrash) * 4, P.s, P.g, rs, (const SelState*)med, h1)));
+  TSA_TRACED("select", P.s,
+             hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, P.s, 1, (const uint64_t*)h1, sb, 0,
+                                (uint64_t)P.volume, scratch, 0, (double*)nullptr));
+  TSA_TRACED("mad_level2", P.s,
+    TSA_DISPATCH(cube->dtype, P.vec, tuning().nt,
+                 hipLaunchKernelGGL((k_mlevel2<DT, VEC, NT>), dim3(P.grid), dim3(P.block), 0, P.s, P.g,
+                                    (const SelState*)med, sb, h2, cand)));
+  TSA_TRACED("select", P.s,
+             hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, P.s, 2, (const uint64_t*)h2, sb, 0,
+                                (uint64_t)P.volume, scratch, 0, (double*)nullptr));
+  TSA_TRACED("mad_level3", P.s,
+    TSA_DISPATCH(cube->dtype, P.vec, tuning().nt,
+                 hipLaunchKernelGGL((k_mlevel3<DT, VEC, NT>), dim3(P.grid), dim3(P.block), 0, P.s, P.g,
+                                    (const SelState*)med, sb, h3, (const uint32_t*)cand)));
+  TSA_TRACED("select", P.s,
+             hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, P.s, 3, (const uint64_t*)h3, sb, 0,
+                                (uint64_t)P.volume, scratch, 0, (double*)nullptr));
+  TSA_TRACED("mad_finish", P.s,
+             hipLaunchKernelGGL(k_mad_finish, dim3(1), dim3(64), 0, P.s, (const SelState*)med, (const SelState*)sb,
+                                cube->dtype, d_out));
+  return launch_ok();
 }
 
 }  // namespace tsa

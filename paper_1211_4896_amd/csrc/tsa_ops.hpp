@@ -242,6 +242,27 @@ TSA_DEV void block_store_var(VarAcc& a, MomShared& sm, Partial* out) {
   }
 }
 
+// ---- |x - m| as the element (median absolute deviation) ----------------------
+// Feeds an accumulator written for float elements with d = |x - m|: one IEEE
+// single-precision subtraction for float32 cubes, exact for int16 cubes (the
+// integer difference is at most 65535, exact in float).  NaN stays NaN.
+template <int DT, class Inner>
+struct AbsDev {
+  Inner inner;
+  float mf;
+  int32_t mi;
+  template <class T>
+  TSA_DEV void operator()(T raw, bool in) {
+    float d;
+    if constexpr (DT == 0)
+      d = fabsf((float)raw - mf);
+    else
+      d = (float)abs((int32_t)raw - mi);
+    inner(d, in);
+  }
+  TSA_DEV void chunk() { inner.chunk(); }
+};
+
 // ---- LDS-privatised counters -------------------------------------------------
 // Every LDS counter array is followed by kTrash spare words (one per lane of a
 // wave) that branch-free increments of invalid lanes may hit; they are never read.
@@ -436,10 +457,9 @@ TSA_DEV void cand_copy_out(const CandSink& k, uint32_t fill) {
   __builtin_amdgcn_wave_barrier();
 }
 
-// Wave-aggregated append of the lanes whose flag is set.
-TSA_DEV void cand_append(bool m, uint32_t key, const CandSink& k) {
-  const uint64_t bal = __ballot(m);
-  if (bal == 0) return;
+// Wave-aggregated append of the lanes whose flag is set (bal = their ballot).
+// Rare, so kept out of line: the unrolled element loops stay small.
+__device__ __attribute__((noinline)) void cand_append_slow(bool m, uint32_t key, uint64_t bal, CandSink k) {
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const uint32_t n = (uint32_t)__popcll(bal);
   uint32_t fill = k.cs->fill[w];
@@ -453,6 +473,11 @@ TSA_DEV void cand_append(bool m, uint32_t key, const CandSink& k) {
   __builtin_amdgcn_wave_barrier();
   if (lane == __ffsll((unsigned long long)act) - 1) k.cs->fill[w] = fill + n;
   __builtin_amdgcn_wave_barrier();
+}
+
+TSA_DEV void cand_append(bool m, uint32_t key, const CandSink& k) {
+  const uint64_t bal = __ballot(m);
+  if (bal != 0) cand_append_slow(m, key, bal, k);
 }
 
 // Whole wave (all lanes active): copy out what is still staged.

@@ -125,3 +125,37 @@ def test_tune_cache_roundtrip(tmp_path):
     assert '"gfx950|f32|nbins=256|nq2=12": [65536, 256, 4, 65536]' in txt
     assert '"gfx950|i16|nbins=128|nq2=3": [16384, 256, 8, 0]' in txt
     assert c.tsa_tune_load(str(tmp_path / "missing.json").encode()) == tsa.TSA_EINVAL
+
+
+def test_minimap_grid_and_workspace():
+    c = tsa.capi()
+    cube = _cube(100, 64, 61)
+    assert c.tsa_minimap_cells(ctypes.byref(cube), 30, 30, 30) == 4 * 3 * 3
+    assert c.tsa_minimap_cells(ctypes.byref(cube), 1000, 1000, 1000) == 1
+    assert c.tsa_minimap_cells(ctypes.byref(cube), 0, 30, 30) == tsa.TSA_EINVAL
+    assert c.tsa_minimap_cells(ctypes.byref(cube), 1, 1, 1) == tsa.TSA_EINVAL  # 390400 cells
+    n1 = c.tsa_minimap_workspace_bytes(ctypes.byref(cube), 30, 30, 30, 64)
+    n2 = c.tsa_workspace_bytes(tsa.OP_REGION_BATCH, ctypes.byref(cube), None, 64, 36)
+    assert n1 >= n2 + 36 * 48 > 0
+    assert c.tsa_minimap_workspace_bytes(ctypes.byref(cube), 30, 30, 30, 0) == 0
+    assert c.tsa_minimap_workspace_bytes(ctypes.byref(cube), 30, 30, 30, 4097) == 0
+    # argument errors come back before anything is launched
+    dummy = ctypes.c_void_p(16)
+    assert c.tsa_minimap(ctypes.byref(cube), 30, 30, 30, 64, dummy, dummy, dummy, 16, None) == tsa.TSA_ENOMEM
+    assert c.tsa_minimap(ctypes.byref(cube), 30, 30, 30, 64, None, dummy, dummy, n1, None) == tsa.TSA_EINVAL
+    assert c.tsa_sigma_count(ctypes.byref(cube), 30, 30, 30, dummy, float("nan"), dummy, None) == tsa.TSA_EINVAL
+    assert c.tsa_sigma_count(ctypes.byref(cube), 30, 30, 30, None, 3.0, dummy, None) == tsa.TSA_EINVAL
+    big = _cube(70000, 70000, 2)
+    assert c.tsa_minimap_cells(ctypes.byref(big), 70000, 70000, 1) == tsa.TSA_EINVAL  # cell >= 2^32 voxels
+
+
+def test_spectrum_arguments_checked_on_host():
+    c = tsa.capi()
+    cube = _cube(16, 16, 16)
+    dummy = ctypes.c_void_p(16)
+    assert c.tsa_spectrum(ctypes.byref(cube), dummy, -1, 4, dummy, None) == tsa.TSA_EINVAL
+    assert c.tsa_spectrum(ctypes.byref(cube), dummy, 4, -1, dummy, None) == tsa.TSA_EINVAL
+    assert c.tsa_spectrum(ctypes.byref(cube), None, 4, 4, dummy, None) == tsa.TSA_EINVAL
+    assert c.tsa_spectrum(ctypes.byref(cube), dummy, 4, 4, None, None) == tsa.TSA_EINVAL
+    assert c.tsa_spectrum(ctypes.byref(cube), None, 0, 4, None, None) == tsa.TSA_OK  # nothing to do
+    assert c.tsa_spectrum(ctypes.byref(cube), dummy, 1 << 30, 1 << 30, dummy, None) == tsa.TSA_EINVAL

@@ -1,0 +1,141 @@
+"""Statistical mini-map and local k-sigma counts (Section 4.5) against the oracle, per cell."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import MEAN_REL, MEAN_RMS, STD_REL, check_hist, check_median, check_moments
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1211_4896_amd as tsa  # noqa: E402
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _dtype(host):
+    return "f32" if host.dtype == np.float32 else "i16"
+
+
+def _check_cells(host, res, hists, cell, nbins, what):
+    nz, ny, nx = host.shape
+    boxes = oracle.minimap_cells((nx, ny, nz), cell)
+    assert len(res) == len(boxes)
+    h = hists.cpu().numpy().view(np.uint64)
+    for i, b in enumerate(boxes):
+        box = tuple(int(v) for v in b)
+        want = oracle.stats(host, nbins, box)
+        r = {k: res[i][k].item() for k in res.dtype.names}
+        tag = f"{what} cell {i} {box}"
+        check_moments(r, want, _dtype(host), tag)
+        check_median(r["median"], want["median"], _dtype(host), tag)
+        assert bool(r["flags"] & tsa.FLAG_HIST_SKIPPED) == want["hist_skipped"], tag
+        if not want["hist_skipped"]:
+            check_hist(h[i], None, want["counts"], None, tag)
+
+
+def _check_sigma(host, got, cell, k, what):
+    """The GPU's cell moments differ from the oracle's within the parity
+    tolerance, so its threshold may move by that much: its count must lie
+    between the oracle's counts at the threshold pushed up and down by the
+    tolerance (these are equal unless a voxel sits that close to it)."""
+    nz, ny, nx = host.shape
+    boxes = oracle.minimap_cells((nx, ny, nz), cell)
+    exact = oracle.sigma_counts(host, cell, k)
+    n_equal = 0
+    for i, b in enumerate(boxes):
+        x0, y0, z0, x1, y1, z1 = (int(v) for v in b)
+        mo = oracle.moments(host, (x0, y0, z0, x1, y1, z1))
+        if mo["count"] == 0:
+            assert got[i] == 0, (what, i)
+            continue
+        thr = mo["mean"] + k * mo["std"]
+        rms = math.hypot(mo["mean"], mo["std"])
+        slack = MEAN_REL * abs(mo["mean"]) + MEAN_RMS * rms + abs(k) * STD_REL * mo["std"] + 4e-16 * abs(thr)
+        v = host[z0:z1, y0:y1, x0:x1].astype(np.float64)
+        lo = np.count_nonzero(v > thr + slack)
+        hi = np.count_nonzero(v > thr - slack)
+        assert lo <= exact[i] <= hi
+        assert lo <= got[i] <= hi, (what, k, i, (x0, y0, z0, x1, y1, z1), int(got[i]), lo, hi, int(exact[i]))
+        n_equal += int(got[i] == exact[i])
+    return n_equal
+
+
+def _run(host, cell, nbins, ks, what):
+    dev = _dev(host)
+    _say("case minimap", what, host.shape, cell, nbins)
+    res, hists, cells_dev = tsa.minimap(dev, cell, nbins)
+    _check_cells(host, res, hists, cell, nbins, what)
+    for k in ks:
+        _say("case sigma", what, k)
+        got = tsa.sigma_count(dev, cell, cells_dev, k)
+        _check_sigma(host, got, cell, k, what)
+    return res, hists, cells_dev, dev
+
+
+def test_minimap_f32_survey_cube():
+    spec = synth.scaled(synth.SPECS["c3"], 128, 96, 70)  # sources + NaN slabs
+    host, _ = synth.generate(spec)
+    _run(host, (30, 30, 30), 64, (2.0, 3.0, 4.0, 7.0, 0.0, -1.5), "c3 30^3")
+
+
+def test_minimap_ragged_cells_and_chunks():
+    rng = np.random.default_rng(8)
+    host = rng.standard_normal((9, 6, 4100)).astype(np.float32)  # two column chunks
+    host[2, :, 100:300] = np.nan
+    host[5, 3, 4097] = 40.0
+    _run(host, (513, 4, 5), 32, (3.0, -0.5), "wide rows")
+    _run(host, (4100, 6, 9), 16, (1.0,), "one cell")
+
+
+def test_minimap_scalar_path_unaligned_rows():
+    rng = np.random.default_rng(9)
+    host = (rng.standard_normal((11, 13, 203)) * 5 + 2).astype(np.float32)  # nx % 4 != 0
+    host[4:6] = np.nan
+    _run(host, (7, 5, 3), 8, (2.0, 0.0), "scalar")
+
+
+def test_minimap_int16():
+    spec = synth.scaled(synth.SPECS["c5c"], 160, 48, 40)
+    host, _ = synth.generate(spec)
+    _run(host, (32, 16, 10), 128, (3.0, 1.0, -2.0), "i16 vec")
+    _run(np.ascontiguousarray(host[:, :, :157]), (30, 7, 11), 16, (2.5,), "i16 scalar")
+
+
+def test_minimap_degenerate_cells_and_ties():
+    rng = np.random.default_rng(10)
+    host = rng.integers(-2, 3, (8, 10, 12)).astype(np.float32)
+    host[0] = 5.0          # constant plane: std 0
+    host[1, :5, :] = np.nan  # cells that are all NaN
+    _run(host, (12, 5, 1), 8, (0.0, 1.0, -1.0), "planes")
+    _run(host, (1, 1, 8), 4, (0.5,), "columns")
+
+
+def test_minimap_deterministic_and_bad_arguments():
+    spec = synth.scaled(synth.SPECS["c1"], 96, 64, 48)
+    host, _ = synth.generate(spec)
+    dev = _dev(host)
+    _say("case minimap determinism")
+    r1, h1, c1 = tsa.minimap(dev, (16, 16, 16), 32)
+    r2, h2, _ = tsa.minimap(dev, (16, 16, 16), 32)
+    assert r1.tobytes() == r2.tobytes() and torch.equal(h1, h2)
+    a1 = tsa.sigma_count(dev, (16, 16, 16), c1, 3.0)
+    a2 = tsa.sigma_count(dev, (16, 16, 16), c1, 3.0)
+    assert np.array_equal(a1, a2)
+    with pytest.raises(tsa.TsaError):
+        tsa.minimap(dev, (1, 1, 1), 32)  # 294912 cells
+    with pytest.raises(tsa.TsaError):
+        tsa.minimap(dev, (0, 16, 16), 32)
+    with pytest.raises(tsa.TsaError):
+        tsa.sigma_count(dev, (16, 16, 16), c1, float("inf"))
