@@ -80,15 +80,6 @@ struct BArgs {
 // ---------------------------------------------------------------------------
 // planning
 // ---------------------------------------------------------------------------
-TSA_DEV Magic dev_magic(uint32_t d) {
-  uint32_t l = 0;
-  while ((1ull << l) < (uint64_t)d) ++l;
-  Magic g;
-  g.m = (uint32_t)((((1ull << 32) * ((1ull << l) - (uint64_t)d)) / (uint64_t)d) + 1ull);
-  g.s1 = l ? 1u : 0u;
-  g.s2 = l ? l - 1u : 0u;
-  return g;
-}
 
 template <int DT>
 __global__ void k_bplan(BArgs a) {
@@ -236,92 +227,6 @@ TSA_DEV bool block_wait_ge(const uint32_t* p, uint32_t v, uint32_t* err, BShared
   return ok;
 }
 
-// Block-wide choice of the digit holding rank k in a histogram of nb bins
-// (u32 counts).  Returns false when k is not inside the histogram.
-TSA_DEV bool block_select_u32(const uint32_t* hist, int nb, uint64_t k, BShared& sh, uint32_t* digit,
-                              uint64_t* cum_before, uint64_t* bucket) {
-  const int t = threadIdx.x, bs = blockDim.x;
-  const int per = (nb + bs - 1) / bs;
-  const int b0 = t * per;
-  uint64_t local = 0;
-  for (int i = 0; i < per; ++i)
-    if (b0 + i < nb) local += hist[b0 + i];
-  const int lane = t % kWave, w = t / kWave;
-  uint64_t inc = local;
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    const uint64_t y = __shfl_up(inc, o);
-    if (lane >= o) inc += y;
-  }
-  if (lane == kWave - 1) sh.wsum[w] = inc;
-  if (t == 0) sh.found = 0;
-  __syncthreads();
-  uint64_t base = inc - local;
-  for (int i = 0; i < w; ++i) base += sh.wsum[i];
-  if (local > 0 && k >= base && k < base + local) {
-    uint64_t cum = base;
-    int d = b0;
-    for (int i = 0; i < per; ++i) {
-      const uint64_t h = (b0 + i < nb) ? hist[b0 + i] : 0;
-      if (k < cum + h) {
-        d = b0 + i;
-        break;
-      }
-      cum += h;
-    }
-    sh.sel_digit = (uint32_t)d;
-    sh.sel_cum = cum;
-    sh.sel_bucket = hist[d];
-    sh.found = 1;
-  }
-  __syncthreads();
-  const bool found = sh.found != 0;
-  *digit = sh.sel_digit;
-  *cum_before = sh.sel_cum;
-  *bucket = sh.sel_bucket;
-  __syncthreads();
-  return found;
-}
-
-TSA_DEV double bvalue_of_key(uint32_t k, int dtype) {
-  return dtype == 0 ? (double)__uint_as_float(f32bits_of_key(k)) : (double)i16_of_key(k);
-}
-
-TSA_DEV void chan_merge_b(double& na, double& ma, double& qa, double nb, double mb, double qb) {
-  if (nb == 0.0) return;
-  if (na == 0.0) {
-    na = nb;
-    ma = mb;
-    qa = qb;
-    return;
-  }
-  const double n = na + nb;
-  const double d = mb - ma;
-  ma = ma + d * (nb / n);
-  qa = qa + qb + d * d * (na * nb / n);
-  na = n;
-}
-
-TSA_DEV void partial_stats_b(const Partial& p, int dtype, double& n, double& m, double& q) {
-  n = (double)p.n;
-  if (p.n == 0) {
-    m = q = 0.0;
-    return;
-  }
-  if (dtype == 0) {
-    const double S = (double)p.sh + (double)p.sl;
-    const double Q = (double)p.qh + (double)p.ql;
-    m = S / n;
-    q = Q - S * m;
-  } else {
-    const __int128 num = (__int128)p.qi * (__int128)p.n - (__int128)p.si * (__int128)p.si;
-    const int64_t hi = (int64_t)(num >> 64);
-    const uint64_t lo = (uint64_t)num;
-    m = (double)p.si / n;
-    q = ((double)hi * 18446744073709551616.0 + (double)lo) / n;
-  }
-}
-
 // ---------------------------------------------------------------------------
 // epilogues (whole block)
 // ---------------------------------------------------------------------------
@@ -384,7 +289,10 @@ TSA_DEV void epilogue1(const BArgs& a, uint32_t q, BShared& sh) {
         R.m2 = 0.0;
         R.std = 0.0;
         R.median = vmin;
-        a.hists[(size_t)q * a.nbins] = cnt;  // lo == hi: every value in bin 0
+        if (isfinite((float)vmin))
+          a.hists[(size_t)q * a.nbins] = cnt;  // lo == hi: every value in bin 0
+        else
+          R.flags |= TSA_FLAG_HIST_SKIPPED;  // an infinite range has no bins
         s.finished = 1;
       } else {
         const double q2 = sh.mq[0] > 0.0 ? sh.mq[0] : 0.0;
@@ -569,7 +477,7 @@ struct BPass1 {
 
 template <int DT>
 struct BPass2 {
-  HistAcc h;
+  HistOwnAcc h;
   Level2Acc<DT> l2;
   VarAcc var;
   bool hist_on, var_on;
@@ -660,7 +568,7 @@ __global__ __launch_bounds__(kBBlock) void k_batch(BArgs a) {
         cand_init(cs);
         __syncthreads();
         const bool hist_on = s.hist_ok != 0, var_on = DT == 0 && s.var_on != 0;
-        BPass2<DT> f{HistAcc{lds, s.lo, s.hi, s.scale, a.nbins - 1, a.rshift, (uint32_t)t & ((1u << a.rshift) - 1u)},
+        BPass2<DT> f{HistOwnAcc{lds, s.lo, s.scale, a.nbins - 1, a.rshift, (uint32_t)t & ((1u << a.rshift) - 1u)},
                      Level2Acc<DT>{l2, s.prefix >> kShift1, s.compact != 0,
                                    CandSink{&cs, a.pool + s.cand_base, &s.cand_fill, s.cand_n}},
                      VarAcc{s.shift, s.vscale}, hist_on, var_on};

@@ -49,6 +49,16 @@ TSA_DEV uint32_t mdiv(uint32_t n, const Magic& g) {
   uint32_t t = __umulhi(n, g.m);
   return (t + ((n - t) >> g.s1)) >> g.s2;
 }
+// The constants of mdiv for divisor d >= 1, computed on the device.
+TSA_DEV Magic dev_magic(uint32_t d) {
+  uint32_t l = 0;
+  while ((1ull << l) < (uint64_t)d) ++l;
+  Magic g;
+  g.m = (uint32_t)((((1ull << 32) * ((1ull << l) - (uint64_t)d)) / (uint64_t)d) + 1ull);
+  g.s1 = l ? 1u : 0u;
+  g.s2 = l ? l - 1u : 0u;
+  return g;
+}
 
 // ---- element types ---------------------------------------------------------
 template <int DT>

@@ -514,7 +514,7 @@ __global__ __launch_bounds__(1024) void k_mid(const Partial* __restrict__ parts,
 
 template <int DT>
 struct PassB {
-  HistAcc h;
+  HistOwnAcc h;
   Level2Acc<DT> l2;
   VarAcc var;
   bool hist_on, var_on;
@@ -547,7 +547,7 @@ __global__ __launch_bounds__(1024) void k_pass_b(Geom g, int32_t nbins, uint32_t
   lds_zero(lds, hsize + kBins2);
   cand_init(cs);
   __syncthreads();
-  PassB<DT> b{HistAcc{lds, st->lo, st->hi, st->scale, nbins - 1, rshift, threadIdx.x & ((1u << rshift) - 1u)},
+  PassB<DT> b{HistOwnAcc{lds, st->lo, st->scale, nbins - 1, rshift, threadIdx.x & ((1u << rshift) - 1u)},
               Level2Acc<DT>{l2, sel_on ? (st->prefix >> kShift1) : 0xFFFFFFFFu, sel_on && st->compact != 0,
                             CandSink{&cs, cand, &st->ncand, st->cand_cap}},
               VarAcc{st->shift, st->vscale}, hist_on, var_on};
@@ -556,7 +556,8 @@ __global__ __launch_bounds__(1024) void k_pass_b(Geom g, int32_t nbins, uint32_t
   __syncthreads();
   if (hist_on) lds_flush(lds, (uint32_t)nbins, rshift, counts);
   if (sel_on) lds_flush(l2, kBins2, 0, hist2);
-  if (hist_on) block_add_outliers(b.h.below, b.h.above, outl, osm);
+  // values lie in their own [min, max]: the outlier counters keep their zeros
+
   if (var_on) block_store_var(b.var, sm, parts2 + blockIdx.x);
 }
 

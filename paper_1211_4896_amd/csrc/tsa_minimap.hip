@@ -3,8 +3,13 @@
 // threshold built from it: per cell, how many voxels lie above the cell's
 // mean + k standard deviations.
 //
-// The cell statistics are a region batch over the grid's boxes (planned on
-// the device, so no box list crosses PCIe).  The threshold pass streams the
+// Cells that fit in LDS (a 30x30x30 float32 cell is 108 KB of the 160 KB a
+// gfx950 workgroup may hold) are answered by one workgroup each: the cell is
+// read from HBM once into LDS, with moments and the first key digit taken on
+// the way in, and the histogram over the cell's own [min, max] and the other
+// two radix digits of the median come from LDS.  Larger cells go through the
+// region batch over the grid's boxes (planned on the device, so no box list
+// crosses PCIe).  The threshold pass streams the
 // cube once in row order: a block owns a band of rows that share one cell row
 // (fixed y and z cell index) and a chunk of up to 4096 columns, so every lane
 // keeps its columns' thresholds and counters in registers for the whole band
@@ -24,11 +29,9 @@ namespace {
 
 constexpr int kMaxCells = 65536;  // the region batch's query limit
 constexpr int kSigBlock = 256;
-constexpr int kSigPos = 4;                                // element groups per lane per row
-constexpr int kSigEPL = 4;                                // elements per group
-constexpr int kSigChunk = kSigBlock * kSigPos * kSigEPL;  // 4096 columns per block
-constexpr int kSigRows = 128;                             // rows per block, at most
-constexpr int kSigUnroll = 4;                             // rows loaded together
+constexpr int kSigEPL = 4;                   // elements per group
+constexpr int kSigChunk = kSigBlock * 4 * kSigEPL;  // widest column chunk of a block (P = 4)
+constexpr int kSigRows = 256;                // rows per block, at most
 
 struct Grid {
   int64_t ncx, ncy, ncz, ncells;
@@ -52,6 +55,16 @@ int grid_of(const tsa_cube* cube, int32_t cx, int32_t cy, int32_t cz, Grid* g) {
 }
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// TSA_MINIMAP_BATCH=1 sends every mini-map through the region batch (for
+// comparing the two paths); otherwise cells that fit in LDS use k_mm_lds.
+bool getenv_lds_path() {
+  static const bool lds = [] {
+    const char* e = getenv("TSA_MINIMAP_BATCH");
+    return !(e && e[0] == '1');
+  }();
+  return lds;
+}
 
 __global__ void k_grid_plan(tsa_region* __restrict__ boxes, int64_t nx, int64_t ny, int64_t nz, int32_t cx,
                             int32_t cy, int32_t cz, int64_t ncx, int64_t ncy, int64_t ncells) {
@@ -110,8 +123,12 @@ TSA_DEV int64_t col_of(int64_t xc0, int t, int e) {
     return xc0 + t + kSigBlock * e;
 }
 
-template <int DT, bool VEC>
+// P element groups of 4 per lane and row (chunk of 1024 P columns), U = 16 / P
+// rows loaded together: 16 loads in flight per lane whatever the row width.
+template <int DT, bool VEC, int P>
 __global__ __launch_bounds__(kSigBlock) void k_sigma(SigArgs a) {
+  constexpr int U = 16 / P;
+  constexpr int64_t CH = (int64_t)kSigBlock * P * kSigEPL;
   __shared__ uint32_t cnt_lds[kSigChunk];
   const int t = threadIdx.x;
   uint64_t b = blockIdx.x;
@@ -126,17 +143,17 @@ __global__ __launch_bounds__(kSigBlock) void k_sigma(SigArgs a) {
   const int64_t r0 = sub * kSigRows;
   if (r0 >= rows) return;  // the same for the whole block, before any barrier
   const int64_t r1 = min(r0 + (int64_t)kSigRows, rows);
-  const int64_t xc0 = xch * kSigChunk, xc1 = min(xc0 + (int64_t)kSigChunk, a.nx);
+  const int64_t xc0 = xch * CH, xc1 = min(xc0 + CH, a.nx);
   const int64_t c_first = xc0 / a.cx;
   const int64_t ncl = (xc1 - 1) / a.cx - c_first + 1;
   const int64_t cell_row = a.ncx * (cyi + a.ncy * czi);
 
   for (int i = t; i < ncl; i += kSigBlock) cnt_lds[i] = 0u;
 
-  float thr[kSigPos * kSigEPL];
-  uint32_t cnt[kSigPos * kSigEPL];
+  float thr[P * kSigEPL];
+  uint32_t cnt[P * kSigEPL];
 #pragma unroll
-  for (int e = 0; e < kSigPos * kSigEPL; ++e) {
+  for (int e = 0; e < P * kSigEPL; ++e) {
     const int64_t x = col_of<VEC>(xc0, t, e);
     thr[e] = x < xc1 ? cell_threshold(a.cells[cell_row + x / a.cx], a.k) : __builtin_nanf("");
     cnt[e] = 0u;
@@ -146,11 +163,11 @@ __global__ __launch_bounds__(kSigBlock) void k_sigma(SigArgs a) {
   const size_t esz = DT == 0 ? 4 : 2;
   const char* base = (const char*)a.base;
   int64_t yy = r0 % rows_y, zz = r0 / rows_y;
-  for (int64_t r = r0; r < r1; r += kSigUnroll) {
-    const char* rowp[kSigUnroll];
-    bool live[kSigUnroll];
+  for (int64_t r = r0; r < r1; r += U) {
+    const char* rowp[U];
+    bool live[U];
 #pragma unroll
-    for (int u = 0; u < kSigUnroll; ++u) {
+    for (int u = 0; u < U; ++u) {
       live[u] = r + u < r1;
       rowp[u] = base + (size_t)(((z0 + zz) * a.ny + (y0 + yy)) * a.nx) * esz;
       if (++yy == rows_y) {
@@ -160,12 +177,12 @@ __global__ __launch_bounds__(kSigBlock) void k_sigma(SigArgs a) {
     }
     if constexpr (VEC) {
       // 16-byte (float32) or 8-byte (int16) groups of 4 elements.
-      uint4 vf[kSigUnroll][kSigPos];
-      uint2 vi[kSigUnroll][kSigPos];
+      uint4 vf[U][P];
+      uint2 vi[U][P];
 #pragma unroll
-      for (int u = 0; u < kSigUnroll; ++u)
+      for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int p = 0; p < kSigPos; ++p) {
+        for (int p = 0; p < P; ++p) {
           const int64_t x = col_of<true>(xc0, t, 4 * p);
           if (live[u] && x < xc1) {
             if constexpr (DT == 0)
@@ -181,9 +198,9 @@ __global__ __launch_bounds__(kSigBlock) void k_sigma(SigArgs a) {
           }
         }
 #pragma unroll
-      for (int u = 0; u < kSigUnroll; ++u)
+      for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int p = 0; p < kSigPos; ++p) {
+        for (int p = 0; p < P; ++p) {
           float v[4];
           if constexpr (DT == 0) {
             v[0] = __uint_as_float(vf[u][p].x);
@@ -201,23 +218,23 @@ __global__ __launch_bounds__(kSigBlock) void k_sigma(SigArgs a) {
           for (int e = 0; e < 4; ++e) cnt[4 * p + e] += (ok && v[e] > thr[4 * p + e]) ? 1u : 0u;
         }
     } else {
-      float v[kSigUnroll][kSigPos * kSigEPL];
+      float v[U][P * kSigEPL];
 #pragma unroll
-      for (int u = 0; u < kSigUnroll; ++u)
+      for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int e = 0; e < kSigPos * kSigEPL; ++e) {
+        for (int e = 0; e < P * kSigEPL; ++e) {
           const int64_t x = col_of<false>(xc0, t, e);
           v[u][e] = (live[u] && x < xc1) ? elem<DT>(rowp[u], x) : __builtin_nanf("");
         }
 #pragma unroll
-      for (int u = 0; u < kSigUnroll; ++u)
+      for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int e = 0; e < kSigPos * kSigEPL; ++e) cnt[e] += v[u][e] > thr[e] ? 1u : 0u;
+        for (int e = 0; e < P * kSigEPL; ++e) cnt[e] += v[u][e] > thr[e] ? 1u : 0u;
     }
   }
 
 #pragma unroll
-  for (int e = 0; e < kSigPos * kSigEPL; ++e) {
+  for (int e = 0; e < P * kSigEPL; ++e) {
     const int64_t x = col_of<VEC>(xc0, t, e);
     if (x < xc1 && cnt[e]) atomicAdd(&cnt_lds[x / a.cx - c_first], cnt[e]);
   }
@@ -226,6 +243,241 @@ __global__ __launch_bounds__(kSigBlock) void k_sigma(SigArgs a) {
     const uint32_t c = cnt_lds[i];
     if (c) atomicAdd((unsigned long long*)&a.above[cell_row + c_first + i], (unsigned long long)c);
   }
+}
+
+// ---- LDS-resident cells ----------------------------------------------------------
+constexpr int kMMBlock = 1024;
+constexpr int kMMLoads = 8;  // global loads in flight per lane while a cell streams in
+
+struct MMArgs {
+  const void* base;
+  int64_t nx, ny, nz;
+  int32_t cx, cy, cz, nbins;
+  int64_t ncx, ncy, ncells, per_xcd;
+  uint32_t rshift, pad;
+  tsa_result* out;
+  uint64_t* hists;
+};
+
+struct MMShared {
+  MomShared mom;
+  Partial part;
+  uint64_t wsum[kMMBlock / kWave];
+  uint32_t found, sel_digit;
+  uint64_t sel_cum, sel_bucket;
+  // the cell's parameters, set by thread 0
+  uint64_t cnt, k;
+  uint32_t kmin, kmax, prefix, go;
+  float lo, hi, scale, shift;
+  uint32_t hist_ok, var_on;
+  int32_t vscale;
+  uint32_t status;
+};
+
+template <int DT>
+TSA_DEV typename Ty<DT>::T mm_elt(uint32_t w) {
+  if constexpr (DT == 0)
+    return __uint_as_float(w);
+  else
+    return (int16_t)(w & 0xFFFFu);
+}
+
+// One workgroup per cell.  Block b works on cell (b % 8) * per_xcd + b / 8, so
+// the cells one XCD (and its L2) sees are neighbours sharing cache lines at
+// their x edges.
+template <int DT>
+__global__ __launch_bounds__(kMMBlock) void k_mm_lds(MMArgs a) {
+  using T = typename Ty<DT>::T;
+  extern __shared__ uint32_t lds[];
+  __shared__ MMShared sh;
+  const int t = threadIdx.x;
+  const int64_t cell = (int64_t)(blockIdx.x % 8u) * a.per_xcd + blockIdx.x / 8u;
+  if (cell >= a.ncells) return;  // the same for the whole block
+  const int64_t ci = cell % a.ncx, cj = (cell / a.ncx) % a.ncy, ck = cell / (a.ncx * a.ncy);
+  const int64_t x0 = ci * a.cx, y0 = cj * a.cy, z0 = ck * a.cz;
+  const uint32_t w = (uint32_t)(min(x0 + (int64_t)a.cx, a.nx) - x0);
+  const uint32_t h = (uint32_t)(min(y0 + (int64_t)a.cy, a.ny) - y0);
+  const uint32_t dd = (uint32_t)(min(z0 + (int64_t)a.cz, a.nz) - z0);
+  const uint32_t nvox = w * h * dd;
+  const Magic mw = dev_magic(w), mh = dev_magic(h);
+  // LDS: data[nvox] | digit counters [kBins1 + kTrash] | histogram [(nbins << rshift) + kTrash]
+  uint32_t* data = lds;
+  uint32_t* dig = lds + ((nvox + 3u) & ~3u);
+  uint32_t* hist = dig + kBins1 + kTrash;
+  const uint32_t hwords = ((uint32_t)a.nbins << a.rshift) + kTrash;
+  for (uint32_t i = t; i < kBins1 + kTrash; i += kMMBlock) dig[i] = 0u;
+  for (uint32_t i = t; i < hwords; i += kMMBlock) hist[i] = 0u;
+  __syncthreads();
+
+  // 1. stream the cell in: moments, min/max keys, first key digit
+  MomAcc<DT> mom;
+  const int64_t plane = a.nx * a.ny;
+  const char* base = (const char*)a.base;
+  for (uint32_t j0 = 0; j0 < nvox; j0 += kMMLoads * kMMBlock) {
+    T raw[kMMLoads];
+#pragma unroll
+    for (int u = 0; u < kMMLoads; ++u) {
+      const uint32_t v = j0 + (uint32_t)(u * kMMBlock + t);
+      if (v < nvox) {
+        const uint32_t row = mdiv(v, mw), lx = v - row * w;
+        const uint32_t lz = mdiv(row, mh), ly = row - lz * h;
+        const int64_t idx = (z0 + lz) * plane + (y0 + ly) * a.nx + x0 + lx;
+        raw[u] = ((const T*)base)[idx];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kMMLoads; ++u) {
+      const uint32_t v = j0 + (uint32_t)(u * kMMBlock + t);
+      if (v < nvox) {
+        mom(raw[u], true);
+        if (Elt<DT>::valid(raw[u], true)) lds_inc(dig, Elt<DT>::key(raw[u]) >> kShift1);
+        if constexpr (DT == 0)
+          data[v] = __float_as_uint(raw[u]);
+        else
+          data[v] = (uint32_t)(uint16_t)raw[u];
+      }
+    }
+  }
+  block_store_partial(mom, sh.mom, &sh.part);  // ends with thread 0 writing sh.part
+  __syncthreads();
+  tsa_result& R = a.out[cell];
+  if (t == 0) {
+    const Partial p = sh.part;
+    double n, mean, m2;
+    partial_stats_b(p, DT, n, mean, m2);
+    R.count = p.n;
+    R.nan_count = nvox - p.n;
+    R.status = TSA_OK;
+    R.flags = 0;
+    sh.cnt = p.n;
+    sh.kmin = p.kmin;
+    sh.kmax = p.kmax;
+    sh.go = 0;
+    sh.hist_ok = 0;
+    sh.var_on = 0;
+    sh.status = TSA_OK;
+    const double qnan = __builtin_nan("");
+    if (p.n == 0) {
+      R.mean = R.m2 = R.std = R.min = R.max = R.median = qnan;
+      R.flags = TSA_FLAG_HIST_SKIPPED;
+    } else {
+      const double vmin = bvalue_of_key(p.kmin, DT), vmax = bvalue_of_key(p.kmax, DT);
+      R.min = vmin;
+      R.max = vmax;
+      const float lo = (float)vmin, hi = (float)vmax;
+      if (p.kmin == p.kmax) {  // constant cell
+        R.mean = vmin;
+        R.m2 = 0.0;
+        R.std = 0.0;
+        R.median = vmin;
+        sh.hist_ok = isfinite(lo) ? 2u : 0u;  // 2: every value in bin 0
+        if (!sh.hist_ok) R.flags = TSA_FLAG_HIST_SKIPPED;
+      } else {
+        if (!(m2 > 0.0)) m2 = 0.0;
+        R.mean = mean;
+        R.m2 = m2;
+        R.std = sqrt(m2 / n);
+        sh.go = 1;
+        sh.k = (p.n - 1) / 2;
+        float scale = 0.f;
+        if (isfinite(lo) && isfinite(hi)) {
+          const float width = hi - lo;
+          if (isfinite(width)) {
+            scale = (float)a.nbins / width;
+            sh.hist_ok = (isfinite(scale) && scale != 0.0f) ? 1u : 0u;
+          }
+        }
+        if (!sh.hist_ok) R.flags = TSA_FLAG_HIST_SKIPPED;
+        sh.lo = lo;
+        sh.hi = hi;
+        sh.scale = scale;
+        sh.var_on = (DT == 0 && isfinite(mean) && one_pass_m2_at_risk(mean, m2 / n, fmax(fabs(vmin), fabs(vmax))))
+                        ? 1u
+                        : 0u;
+        sh.shift = sh.var_on ? (float)mean : 0.0f;
+        sh.vscale = sh.var_on ? var_scale_exp(fmax(fabs(vmax - (double)sh.shift), fabs(vmin - (double)sh.shift))) : 0;
+      }
+    }
+  }
+  __syncthreads();
+  const bool go = sh.go != 0;
+  if (go) {
+    // 2. first digit, then histogram + second digit (+ M2 about the mean) from LDS
+    uint32_t d1, d2, d3;
+    uint64_t cum, bucket;
+    bool found = block_select_u32(dig, kBins1, sh.k, sh, &d1, &cum, &bucket);
+    uint64_t k = sh.k - cum;
+    for (uint32_t i = t; i < kBins2; i += kMMBlock) dig[i] = 0u;
+    __syncthreads();
+    HistOwnAcc hacc{hist, sh.lo, sh.scale, a.nbins - 1, a.rshift, (uint32_t)t & ((1u << a.rshift) - 1u)};
+    VarAcc var{sh.shift, sh.vscale};
+    const bool hist_on = sh.hist_ok != 0, var_on = sh.var_on != 0;
+    for (uint32_t v = t; v < nvox; v += kMMBlock) {
+      const T x = mm_elt<DT>(data[v]);
+      if (hist_on) hacc(x, true);
+      const uint32_t key = Elt<DT>::key(x);
+      if (Elt<DT>::valid(x, true) && (key >> kShift1) == d1) lds_inc(dig, (key >> kShift2) & 0xFFFu);
+      if constexpr (DT == 0) {
+        if (var_on) var(x, true);
+      }
+    }
+    if (var_on) block_store_var(var, sh.mom, &sh.part);
+    __syncthreads();
+    if (t == 0 && var_on) {
+      const double n = (double)sh.cnt;
+      const double dm = R.mean - (double)sh.shift;
+      double m2 = ldexp((double)sh.part.qh + (double)sh.part.ql, -2 * sh.vscale) - n * dm * dm;
+      if (!(m2 > 0.0)) m2 = 0.0;
+      R.m2 = m2;
+      R.std = sqrt(m2 / n);
+    }
+    found = block_select_u32(dig, kBins2, k, sh, &d2, &cum, &bucket) && found;
+    k -= cum;
+    const uint32_t prefix = (d1 << kShift1) | (d2 << kShift2);
+    if constexpr (DT == 0) {
+      // 3. last 8 bits over the keys of the second-digit bucket
+      for (uint32_t i = t; i < kBins3; i += kMMBlock) dig[i] = 0u;
+      __syncthreads();
+      const uint32_t p2 = prefix >> kShift2;
+      for (uint32_t v = t; v < nvox; v += kMMBlock) {
+        const float x = __uint_as_float(data[v]);
+        const uint32_t key = Elt<0>::key(x);
+        if (x == x && (key >> kShift2) == p2) lds_inc(dig, key & 0xFFu);
+      }
+      __syncthreads();
+      found = block_select_u32(dig, kBins3, k, sh, &d3, &cum, &bucket) && found;
+    } else {
+      d3 = 0;  // int16 keys have no bits below the second digit
+    }
+    if (t == 0) {
+      if (found)
+        R.median = bvalue_of_key(prefix | d3, DT);
+      else {
+        R.median = __builtin_nan("");
+        R.status = TSA_EDEVICE;
+      }
+    }
+  }
+  __syncthreads();
+  // 4. the cell's histogram (every bin written)
+  uint64_t* H = a.hists + cell * (int64_t)a.nbins;
+  const uint32_t ok = sh.hist_ok, R1 = 1u << a.rshift;
+  for (int32_t b = t; b < a.nbins; b += kMMBlock) {
+    uint64_t c = 0;
+    if (ok == 1) {
+      for (uint32_t r = 0; r < R1; ++r) c += hist[((uint32_t)b << a.rshift) + r];
+    } else if (ok == 2 && b == 0) {
+      c = sh.cnt;
+    }
+    H[b] = c;
+  }
+}
+
+// LDS bytes of k_mm_lds for a cell of nvox voxels (0: does not fit).
+size_t mm_lds_bytes(uint64_t nvox, int32_t nbins, uint32_t rshift, size_t budget) {
+  const size_t words = ((nvox + 3u) & ~(uint64_t)3u) + kBins1 + kTrash + ((size_t)nbins << rshift) + kTrash;
+  const size_t bytes = words * 4 + sizeof(MMShared) + 1024;  // + static LDS and slack
+  return bytes <= budget ? words * 4 : 0;
 }
 
 __global__ void k_zero64(uint64_t* __restrict__ p, int64_t n) {
@@ -253,6 +505,50 @@ int run_minimap(const tsa_cube* cube, int32_t cx, int32_t cy, int32_t cz, int32_
   if (!need) return TSA_EINVAL;
   if (!d_ws || ws_bytes < need) return TSA_ENOMEM;
   hipStream_t s = (hipStream_t)stream;
+  if (getenv_lds_path()) {
+    DevInfo dev;
+    if ((st = device_info(&dev))) return st;
+    const uint64_t nvox = (uint64_t)(cx < cube->nx ? cx : cube->nx) * (uint64_t)(cy < cube->ny ? cy : cube->ny) *
+                          (uint64_t)(cz < cube->nz ? cz : cube->nz);
+    uint32_t rshift = nbins <= 256 ? 2u : nbins <= 1024 ? 1u : 0u;
+    size_t lds = 0;
+    for (;; --rshift) {
+      lds = mm_lds_bytes(nvox, nbins, rshift, dev.lds_per_block);
+      if (lds || rshift == 0) break;
+    }
+    if (lds) {
+      MMArgs m;
+      m.base = cube->data;
+      m.nx = cube->nx;
+      m.ny = cube->ny;
+      m.nz = cube->nz;
+      m.cx = cx;
+      m.cy = cy;
+      m.cz = cz;
+      m.nbins = nbins;
+      m.ncx = g.ncx;
+      m.ncy = g.ncy;
+      m.ncells = g.ncells;
+      m.per_xcd = (g.ncells + 7) / 8;
+      m.rshift = rshift;
+      m.pad = 0;
+      m.out = d_cells;
+      m.hists = d_hists;
+      const dim3 grid((uint32_t)(m.per_xcd * 8));
+      if (cube->dtype == TSA_F32) {
+        if (lds > 65536 && hipFuncSetAttribute((const void*)k_mm_lds<0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)lds) != hipSuccess)
+          return TSA_EDEVICE;
+        TSA_TRACED("minimap_lds", s, hipLaunchKernelGGL(k_mm_lds<0>, grid, dim3(kMMBlock), lds, s, m));
+      } else {
+        if (lds > 65536 && hipFuncSetAttribute((const void*)k_mm_lds<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)lds) != hipSuccess)
+          return TSA_EDEVICE;
+        TSA_TRACED("minimap_lds", s, hipLaunchKernelGGL(k_mm_lds<1>, grid, dim3(kMMBlock), lds, s, m));
+      }
+      return hipGetLastError() == hipSuccess ? TSA_OK : TSA_EDEVICE;
+    }
+  }
   tsa_region* boxes = (tsa_region*)d_ws;
   const size_t off = align256(sizeof(tsa_region) * (size_t)g.ncells);
   const int blocks = (int)((g.ncells + 255) / 256);
@@ -281,7 +577,9 @@ int run_sigma_count(const tsa_cube* cube, int32_t cx, int32_t cy, int32_t cz, co
   a.cz = cz;
   a.ncx = g.ncx;
   a.ncy = g.ncy;
-  a.nchunk = (cube->nx + kSigChunk - 1) / kSigChunk;
+  const int P = cube->nx <= 1024 ? 1 : cube->nx <= 2048 ? 2 : 4;
+  const int64_t chunk = (int64_t)kSigBlock * P * kSigEPL;
+  a.nchunk = (cube->nx + chunk - 1) / chunk;
   const int64_t band_rows = (int64_t)(cy < cube->ny ? cy : cube->ny) * (int64_t)(cz < cube->nz ? cz : cube->nz);
   const int64_t subs = (band_rows + kSigRows - 1) / kSigRows;
   const double nblocks = (double)subs * (double)a.nchunk * (double)g.ncy * (double)g.ncz;
@@ -295,17 +593,30 @@ int run_sigma_count(const tsa_cube* cube, int32_t cx, int32_t cy, int32_t cz, co
   const uintptr_t group_align = cube->dtype == TSA_F32 ? 16 : 8;  // bytes of a 4-element group
   const bool vec = ((uintptr_t)cube->data % group_align) == 0 && (cube->nx % 4) == 0;
   const dim3 grid((uint32_t)nblocks);
+#define TSA_SIGMA_LAUNCH(DTV, VECV, PV) \
+  TSA_TRACED("sigma", s, hipLaunchKernelGGL((k_sigma<DTV, VECV, PV>), grid, dim3(kSigBlock), 0, s, a))
+#define TSA_SIGMA_BY_P(DTV, VECV)      \
+  do {                                 \
+    if (P == 1)                        \
+      TSA_SIGMA_LAUNCH(DTV, VECV, 1);  \
+    else if (P == 2)                   \
+      TSA_SIGMA_LAUNCH(DTV, VECV, 2);  \
+    else                               \
+      TSA_SIGMA_LAUNCH(DTV, VECV, 4);  \
+  } while (0)
   if (cube->dtype == TSA_F32) {
     if (vec)
-      TSA_TRACED("sigma", s, hipLaunchKernelGGL((k_sigma<0, true>), grid, dim3(kSigBlock), 0, s, a));
+      TSA_SIGMA_BY_P(0, true);
     else
-      TSA_TRACED("sigma", s, hipLaunchKernelGGL((k_sigma<0, false>), grid, dim3(kSigBlock), 0, s, a));
+      TSA_SIGMA_BY_P(0, false);
   } else {
     if (vec)
-      TSA_TRACED("sigma", s, hipLaunchKernelGGL((k_sigma<1, true>), grid, dim3(kSigBlock), 0, s, a));
+      TSA_SIGMA_BY_P(1, true);
     else
-      TSA_TRACED("sigma", s, hipLaunchKernelGGL((k_sigma<1, false>), grid, dim3(kSigBlock), 0, s, a));
+      TSA_SIGMA_BY_P(1, false);
   }
+#undef TSA_SIGMA_BY_P
+#undef TSA_SIGMA_LAUNCH
   return hipGetLastError() == hipSuccess ? TSA_OK : TSA_EDEVICE;
 }
 

@@ -321,6 +321,27 @@ struct HistAcc {
   TSA_DEV void chunk() {}
 };
 
+// Histogram over the values' own [min, max] (lo and hi are the extremes of the
+// same values, both finite): every valid value is in range, so only NaN needs a
+// test, (v - lo) * scale is never negative, and there are no outliers.  Gives
+// the same bins as HistAcc for such a range.
+struct HistOwnAcc {
+  uint32_t* lds;
+  float lo, scale;
+  int32_t nbm1;
+  uint32_t rshift, rep;
+  template <class T>
+  TSA_DEV void operator()(T raw, bool in) {
+    const float v = (float)raw;  // exact for int16
+    if (in && v == v) {
+      const float t = (v - lo) * scale;  // lo == hi: scale == 0 and t == 0
+      const int32_t b = min((int32_t)t, nbm1);
+      lds_inc(lds, ((uint32_t)b << rshift) + rep);
+    }
+  }
+  TSA_DEV void chunk() {}
+};
+
 // ---- histogram with 16-bit LDS counters (up to 65536 bins) ---------------------
 // Bins [b0, b0+nb) live as 16-bit halves of LDS words; every `epoch` calls of
 // chunk() the block adds its non-zero counters to the global uint64 bins and
@@ -394,6 +415,95 @@ TSA_DEV void block_add_outliers(uint32_t below, uint32_t above, uint64_t* g, uin
   }
 }
 
+// ---- digit selection and moment merges (whole block / one thread) -----------
+// Block-wide choice of the digit holding rank k in a histogram of nb bins
+// (u32 counts).  Returns false when k is not inside the histogram.  SH provides
+// wsum[blockDim.x / 64], found, sel_digit, sel_cum and sel_bucket in LDS.
+template <class SH>
+TSA_DEV bool block_select_u32(const uint32_t* hist, int nb, uint64_t k, SH& sh, uint32_t* digit,
+                              uint64_t* cum_before, uint64_t* bucket) {
+  const int t = threadIdx.x, bs = blockDim.x;
+  const int per = (nb + bs - 1) / bs;
+  const int b0 = t * per;
+  uint64_t local = 0;
+  for (int i = 0; i < per; ++i)
+    if (b0 + i < nb) local += hist[b0 + i];
+  const int lane = t % kWave, w = t / kWave;
+  uint64_t inc = local;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint64_t y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
+  }
+  if (lane == kWave - 1) sh.wsum[w] = inc;
+  if (t == 0) sh.found = 0;
+  __syncthreads();
+  uint64_t base = inc - local;
+  for (int i = 0; i < w; ++i) base += sh.wsum[i];
+  if (local > 0 && k >= base && k < base + local) {
+    uint64_t cum = base;
+    int d = b0;
+    for (int i = 0; i < per; ++i) {
+      const uint64_t h = (b0 + i < nb) ? hist[b0 + i] : 0;
+      if (k < cum + h) {
+        d = b0 + i;
+        break;
+      }
+      cum += h;
+    }
+    sh.sel_digit = (uint32_t)d;
+    sh.sel_cum = cum;
+    sh.sel_bucket = hist[d];
+    sh.found = 1;
+  }
+  __syncthreads();
+  const bool found = sh.found != 0;
+  *digit = sh.sel_digit;
+  *cum_before = sh.sel_cum;
+  *bucket = sh.sel_bucket;
+  __syncthreads();
+  return found;
+}
+
+TSA_DEV double bvalue_of_key(uint32_t k, int dtype) {
+  return dtype == 0 ? (double)__uint_as_float(f32bits_of_key(k)) : (double)i16_of_key(k);
+}
+
+TSA_DEV void chan_merge_b(double& na, double& ma, double& qa, double nb, double mb, double qb) {
+  if (nb == 0.0) return;
+  if (na == 0.0) {
+    na = nb;
+    ma = mb;
+    qa = qb;
+    return;
+  }
+  const double n = na + nb;
+  const double d = mb - ma;
+  ma = ma + d * (nb / n);
+  qa = qa + qb + d * d * (na * nb / n);
+  na = n;
+}
+
+TSA_DEV void partial_stats_b(const Partial& p, int dtype, double& n, double& m, double& q) {
+  n = (double)p.n;
+  if (p.n == 0) {
+    m = q = 0.0;
+    return;
+  }
+  if (dtype == 0) {
+    const double S = (double)p.sh + (double)p.sl;
+    const double Q = (double)p.qh + (double)p.ql;
+    m = S / n;
+    q = Q - S * m;
+  } else {
+    const __int128 num = (__int128)p.qi * (__int128)p.n - (__int128)p.si * (__int128)p.si;
+    const int64_t hi = (int64_t)(num >> 64);
+    const uint64_t lo = (uint64_t)num;
+    m = (double)p.si / n;
+    q = ((double)hi * 18446744073709551616.0 + (double)lo) / n;
+  }
+}
+
 // ---- radix digits of the key (Section 4.3 replaced by radix selection) --------
 template <int DT>
 struct Digit1Acc {  // top 12 key bits of every valid element
@@ -458,8 +568,9 @@ TSA_DEV void cand_copy_out(const CandSink& k, uint32_t fill) {
 }
 
 // Wave-aggregated append of the lanes whose flag is set (bal = their ballot).
-// Rare, so kept out of line: the unrolled element loops stay small.
-__device__ __attribute__((noinline)) void cand_append_slow(bool m, uint32_t key, uint64_t bal, CandSink k) {
+// Kept inline: an out-of-line call costs the element loops more than its
+// code size saves (measured on the fused pass B).
+TSA_DEV void cand_append_slow(bool m, uint32_t key, uint64_t bal, const CandSink& k) {
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const uint32_t n = (uint32_t)__popcll(bal);
   uint32_t fill = k.cs->fill[w];

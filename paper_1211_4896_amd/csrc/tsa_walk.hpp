@@ -119,8 +119,8 @@ TSA_DEV void walk(const Geom& g, F& f) {
 #pragma unroll
             for (int e = 0; e < TT::EPV; ++e) f(TT::get(r[u], e), true);
           }
-        } else {  // the last, partial chunk of a block: not unrolled, to keep the code small
-#pragma unroll 1
+        } else {  // the last, partial chunk of a block
+#pragma unroll
           for (int u = 0; u < U; ++u) {
             const int64_t j = i + u * bs;
             if (j < g.v1) {

@@ -108,12 +108,17 @@ def test_batch_adversarial_cube():
     host[3:5] = np.nan  # NaN slab
     host[10, :, :] = 7.0  # constant plane
     host[12, 5, 5] = -0.0
+    host[14, 0:2, :] = np.inf   # constant +inf rows
+    host[14, 2:4, :] = -np.inf  # constant -inf rows
     dev = _dev(host)
     boxes = np.array([[0, 0, 3, 40, 24, 5],      # all NaN
                       [0, 0, 10, 40, 24, 11],    # constant
                       [0, 0, 0, 40, 24, 16],     # everything
                       [5, 5, 12, 6, 6, 13],      # a single -0
-                      [1, 2, 2, 39, 22, 14]], dtype=np.int64)
+                      [1, 2, 2, 39, 22, 14],
+                      [0, 0, 14, 40, 2, 15],     # constant +inf: no histogram
+                      [3, 2, 14, 9, 4, 15],      # constant -inf: no histogram
+                      [0, 1, 14, 40, 3, 15]], dtype=np.int64)  # +inf and -inf
     _say("case batch adversarial")
     _check_batch(host, dev, boxes, 8, what="adv")
 

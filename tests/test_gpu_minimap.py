@@ -118,6 +118,8 @@ def test_minimap_degenerate_cells_and_ties():
     host = rng.integers(-2, 3, (8, 10, 12)).astype(np.float32)
     host[0] = 5.0          # constant plane: std 0
     host[1, :5, :] = np.nan  # cells that are all NaN
+    host[2, :5, :] = np.inf  # constant +inf cells: no histogram
+    host[3, 5:, :] = -np.inf
     _run(host, (12, 5, 1), 8, (0.0, 1.0, -1.0), "planes")
     _run(host, (1, 1, 8), 4, (0.5,), "columns")
 
