@@ -3,13 +3,13 @@
 // threshold built from it: per cell, how many voxels lie above the cell's
 // mean + k standard deviations.
 //
-// Cells that fit in LDS (a 30x30x30 float32 cell is 108 KB of the 160 KB a
-// gfx950 workgroup may hold) are answered by one workgroup each: the cell is
-// read from HBM once into LDS, with moments and the first key digit taken on
-// the way in, and the histogram over the cell's own [min, max] and the other
-// two radix digits of the median come from LDS.  Larger cells go through the
-// region batch over the grid's boxes (planned on the device, so no box list
-// crosses PCIe).  The threshold pass streams the
+// Cells of at most 32768 voxels (a 30x30x30 cell is 27000) are answered by one
+// 1024-lane workgroup each, the cell read from HBM once into registers (up to
+// 32 values per lane): moments and the first key digit, then the histogram
+// over the cell's own [min, max] and the other two radix digits of the median,
+// all from registers, with only the counters in LDS.  Larger cells go through
+// the region batch over the grid's boxes (planned on the device, so no box
+// list crosses PCIe).  The threshold pass streams the
 // cube once in row order: a block owns a band of rows that share one cell row
 // (fixed y and z cell index) and a chunk of up to 4096 columns, so every lane
 // keeps its columns' thresholds and counters in registers for the whole band
@@ -57,13 +57,14 @@ int grid_of(const tsa_cube* cube, int32_t cx, int32_t cy, int32_t cz, Grid* g) {
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // TSA_MINIMAP_BATCH=1 sends every mini-map through the region batch (for
-// comparing the two paths); otherwise cells that fit in LDS use k_mm_lds.
-bool getenv_lds_path() {
-  static const bool lds = [] {
+// comparing the two paths); otherwise cells of at most 32768 voxels use the
+// register-resident k_mm_reg.
+bool register_path_on() {
+  static const bool on = [] {
     const char* e = getenv("TSA_MINIMAP_BATCH");
     return !(e && e[0] == '1');
   }();
-  return lds;
+  return on;
 }
 
 __global__ void k_grid_plan(tsa_region* __restrict__ boxes, int64_t nx, int64_t ny, int64_t nz, int32_t cx,
@@ -247,7 +248,6 @@ __global__ __launch_bounds__(kSigBlock) void k_sigma(SigArgs a) {
 
 // ---- LDS-resident cells ----------------------------------------------------------
 constexpr int kMMBlock = 1024;
-constexpr int kMMLoads = 8;  // global loads in flight per lane while a cell streams in
 
 struct MMArgs {
   const void* base;
@@ -274,21 +274,19 @@ struct MMShared {
   uint32_t status;
 };
 
-template <int DT>
-TSA_DEV typename Ty<DT>::T mm_elt(uint32_t w) {
-  if constexpr (DT == 0)
-    return __uint_as_float(w);
-  else
-    return (int16_t)(w & 0xFFFFu);
-}
-
-// One workgroup per cell.  Block b works on cell (b % 8) * per_xcd + b / 8, so
-// the cells one XCD (and its L2) sees are neighbours sharing cache lines at
+// One workgroup per cell, the cell held in registers: lane t keeps voxels
+// t + 1024 j (j < EPT) of the cell, so a 30^3 cell is 27 values per lane, all
+// loaded at once, and the LDS holds only counters.  The float-float moments
+// over the cell's values bound this kernel by VALU issue, not by HBM.
+// Every value is held as float32: int16 converts exactly, its float-float sums
+// stay exact (partial sums below 2^48) and float keys order it the same way,
+// and slots past the cell hold NaN, so no per-slot validity test is needed.  Block b works on cell (b % 8) * per_xcd + b / 8,
+// so the cells one XCD (and its L2) sees are neighbours sharing cache lines at
 // their x edges.
-template <int DT>
-__global__ __launch_bounds__(kMMBlock) void k_mm_lds(MMArgs a) {
+template <int DT, int EPT>
+__global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
   using T = typename Ty<DT>::T;
-  extern __shared__ uint32_t lds[];
+  extern __shared__ uint32_t lds[];  // digit counters [kBins1 + kTrash] | histogram [(nbins << rshift) + kTrash]
   __shared__ MMShared sh;
   const int t = threadIdx.x;
   const int64_t cell = (int64_t)(blockIdx.x % 8u) * a.per_xcd + blockIdx.x / 8u;
@@ -298,45 +296,38 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_lds(MMArgs a) {
   const uint32_t w = (uint32_t)(min(x0 + (int64_t)a.cx, a.nx) - x0);
   const uint32_t h = (uint32_t)(min(y0 + (int64_t)a.cy, a.ny) - y0);
   const uint32_t dd = (uint32_t)(min(z0 + (int64_t)a.cz, a.nz) - z0);
-  const uint32_t nvox = w * h * dd;
-  const Magic mw = dev_magic(w), mh = dev_magic(h);
-  // LDS: data[nvox] | digit counters [kBins1 + kTrash] | histogram [(nbins << rshift) + kTrash]
-  uint32_t* data = lds;
-  uint32_t* dig = lds + ((nvox + 3u) & ~3u);
-  uint32_t* hist = dig + kBins1 + kTrash;
+  const uint32_t nvox = w * h * dd;  // <= EPT * kMMBlock (checked on the host)
+  uint32_t* dig = lds;
+  uint32_t* hist = lds + kBins1 + kTrash;
   const uint32_t hwords = ((uint32_t)a.nbins << a.rshift) + kTrash;
   for (uint32_t i = t; i < kBins1 + kTrash; i += kMMBlock) dig[i] = 0u;
   for (uint32_t i = t; i < hwords; i += kMMBlock) hist[i] = 0u;
-  __syncthreads();
 
-  // 1. stream the cell in: moments, min/max keys, first key digit
-  MomAcc<DT> mom;
-  const int64_t plane = a.nx * a.ny;
-  const char* base = (const char*)a.base;
-  for (uint32_t j0 = 0; j0 < nvox; j0 += kMMLoads * kMMBlock) {
-    T raw[kMMLoads];
+  // 1. every load of the lane in flight at once
+  float x[EPT];
+  {
+    const Magic mw = dev_magic(w), mh = dev_magic(h);
+    const T* base = (const T*)a.base;
+    const int64_t plane = a.nx * a.ny;
 #pragma unroll
-    for (int u = 0; u < kMMLoads; ++u) {
-      const uint32_t v = j0 + (uint32_t)(u * kMMBlock + t);
+    for (int j = 0; j < EPT; ++j) {
+      const uint32_t v = (uint32_t)(j * kMMBlock + t);
       if (v < nvox) {
         const uint32_t row = mdiv(v, mw), lx = v - row * w;
         const uint32_t lz = mdiv(row, mh), ly = row - lz * h;
-        const int64_t idx = (z0 + lz) * plane + (y0 + ly) * a.nx + x0 + lx;
-        raw[u] = ((const T*)base)[idx];
+        x[j] = (float)base[(z0 + lz) * plane + (y0 + ly) * a.nx + x0 + lx];
+      } else {
+        x[j] = __builtin_nanf("");
       }
     }
+  }
+  __syncthreads();  // counters cleared
+  // moments, min/max keys and the first key digit
+  MomAcc<0> mom;
 #pragma unroll
-    for (int u = 0; u < kMMLoads; ++u) {
-      const uint32_t v = j0 + (uint32_t)(u * kMMBlock + t);
-      if (v < nvox) {
-        mom(raw[u], true);
-        if (Elt<DT>::valid(raw[u], true)) lds_inc(dig, Elt<DT>::key(raw[u]) >> kShift1);
-        if constexpr (DT == 0)
-          data[v] = __float_as_uint(raw[u]);
-        else
-          data[v] = (uint32_t)(uint16_t)raw[u];
-      }
-    }
+  for (int j = 0; j < EPT; ++j) {
+    mom(x[j], true);
+    if (x[j] == x[j]) lds_inc(dig, key_f32(__float_as_uint(x[j])) >> kShift1);
   }
   block_store_partial(mom, sh.mom, &sh.part);  // ends with thread 0 writing sh.part
   __syncthreads();
@@ -344,24 +335,21 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_lds(MMArgs a) {
   if (t == 0) {
     const Partial p = sh.part;
     double n, mean, m2;
-    partial_stats_b(p, DT, n, mean, m2);
+    partial_stats_b(p, 0, n, mean, m2);
     R.count = p.n;
     R.nan_count = nvox - p.n;
     R.status = TSA_OK;
     R.flags = 0;
     sh.cnt = p.n;
-    sh.kmin = p.kmin;
-    sh.kmax = p.kmax;
     sh.go = 0;
     sh.hist_ok = 0;
     sh.var_on = 0;
-    sh.status = TSA_OK;
     const double qnan = __builtin_nan("");
     if (p.n == 0) {
       R.mean = R.m2 = R.std = R.min = R.max = R.median = qnan;
       R.flags = TSA_FLAG_HIST_SKIPPED;
     } else {
-      const double vmin = bvalue_of_key(p.kmin, DT), vmax = bvalue_of_key(p.kmax, DT);
+      const double vmin = bvalue_of_key(p.kmin, 0), vmax = bvalue_of_key(p.kmax, 0);
       R.min = vmin;
       R.max = vmax;
       const float lo = (float)vmin, hi = (float)vmax;
@@ -389,9 +377,8 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_lds(MMArgs a) {
         }
         if (!sh.hist_ok) R.flags = TSA_FLAG_HIST_SKIPPED;
         sh.lo = lo;
-        sh.hi = hi;
         sh.scale = scale;
-        sh.var_on = (DT == 0 && isfinite(mean) && one_pass_m2_at_risk(mean, m2 / n, fmax(fabs(vmin), fabs(vmax))))
+        sh.var_on = (isfinite(mean) && one_pass_m2_at_risk(mean, m2 / n, fmax(fabs(vmin), fabs(vmax))))
                         ? 1u
                         : 0u;
         sh.shift = sh.var_on ? (float)mean : 0.0f;
@@ -400,9 +387,8 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_lds(MMArgs a) {
     }
   }
   __syncthreads();
-  const bool go = sh.go != 0;
-  if (go) {
-    // 2. first digit, then histogram + second digit (+ M2 about the mean) from LDS
+  if (sh.go) {
+    // 2. first digit; histogram over [min, max] + second digit (+ M2 about the mean)
     uint32_t d1, d2, d3;
     uint64_t cum, bucket;
     bool found = block_select_u32(dig, kBins1, sh.k, sh, &d1, &cum, &bucket);
@@ -412,14 +398,12 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_lds(MMArgs a) {
     HistOwnAcc hacc{hist, sh.lo, sh.scale, a.nbins - 1, a.rshift, (uint32_t)t & ((1u << a.rshift) - 1u)};
     VarAcc var{sh.shift, sh.vscale};
     const bool hist_on = sh.hist_ok != 0, var_on = sh.var_on != 0;
-    for (uint32_t v = t; v < nvox; v += kMMBlock) {
-      const T x = mm_elt<DT>(data[v]);
-      if (hist_on) hacc(x, true);
-      const uint32_t key = Elt<DT>::key(x);
-      if (Elt<DT>::valid(x, true) && (key >> kShift1) == d1) lds_inc(dig, (key >> kShift2) & 0xFFFu);
-      if constexpr (DT == 0) {
-        if (var_on) var(x, true);
-      }
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      if (hist_on) hacc(x[j], true);
+      const uint32_t key = key_f32(__float_as_uint(x[j]));
+      lds_inc_rare(dig, x[j] == x[j] && (key >> kShift1) == d1, (key >> kShift2) & 0xFFFu);
+      if (var_on) var(x[j], true);
     }
     if (var_on) block_store_var(var, sh.mom, &sh.part);
     __syncthreads();
@@ -434,24 +418,20 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_lds(MMArgs a) {
     found = block_select_u32(dig, kBins2, k, sh, &d2, &cum, &bucket) && found;
     k -= cum;
     const uint32_t prefix = (d1 << kShift1) | (d2 << kShift2);
-    if constexpr (DT == 0) {
-      // 3. last 8 bits over the keys of the second-digit bucket
-      for (uint32_t i = t; i < kBins3; i += kMMBlock) dig[i] = 0u;
-      __syncthreads();
-      const uint32_t p2 = prefix >> kShift2;
-      for (uint32_t v = t; v < nvox; v += kMMBlock) {
-        const float x = __uint_as_float(data[v]);
-        const uint32_t key = Elt<0>::key(x);
-        if (x == x && (key >> kShift2) == p2) lds_inc(dig, key & 0xFFu);
-      }
-      __syncthreads();
-      found = block_select_u32(dig, kBins3, k, sh, &d3, &cum, &bucket) && found;
-    } else {
-      d3 = 0;  // int16 keys have no bits below the second digit
+    // 3. last 8 bits over the keys of the second-digit bucket
+    for (uint32_t i = t; i < kBins3; i += kMMBlock) dig[i] = 0u;
+    __syncthreads();
+    const uint32_t p2 = prefix >> kShift2;
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const uint32_t key = key_f32(__float_as_uint(x[j]));
+      lds_inc_rare(dig, x[j] == x[j] && (key >> kShift2) == p2, key & 0xFFu);
     }
+    __syncthreads();
+    found = block_select_u32(dig, kBins3, k, sh, &d3, &cum, &bucket) && found;
     if (t == 0) {
       if (found)
-        R.median = bvalue_of_key(prefix | d3, DT);
+        R.median = bvalue_of_key(prefix | d3, 0);
       else {
         R.median = __builtin_nan("");
         R.status = TSA_EDEVICE;
@@ -473,11 +453,12 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_lds(MMArgs a) {
   }
 }
 
-// LDS bytes of k_mm_lds for a cell of nvox voxels (0: does not fit).
-size_t mm_lds_bytes(uint64_t nvox, int32_t nbins, uint32_t rshift, size_t budget) {
-  const size_t words = ((nvox + 3u) & ~(uint64_t)3u) + kBins1 + kTrash + ((size_t)nbins << rshift) + kTrash;
-  const size_t bytes = words * 4 + sizeof(MMShared) + 1024;  // + static LDS and slack
-  return bytes <= budget ? words * 4 : 0;
+// Values per lane needed for a cell of nvox voxels (0: more than the register path holds).
+int mm_ept(uint64_t nvox) {
+  if (nvox <= 8u * kMMBlock) return 8;
+  if (nvox <= 16u * kMMBlock) return 16;
+  if (nvox <= 32u * kMMBlock) return 32;
+  return 0;
 }
 
 __global__ void k_zero64(uint64_t* __restrict__ p, int64_t n) {
@@ -505,49 +486,51 @@ int run_minimap(const tsa_cube* cube, int32_t cx, int32_t cy, int32_t cz, int32_
   if (!need) return TSA_EINVAL;
   if (!d_ws || ws_bytes < need) return TSA_ENOMEM;
   hipStream_t s = (hipStream_t)stream;
-  if (getenv_lds_path()) {
-    DevInfo dev;
-    if ((st = device_info(&dev))) return st;
-    const uint64_t nvox = (uint64_t)(cx < cube->nx ? cx : cube->nx) * (uint64_t)(cy < cube->ny ? cy : cube->ny) *
-                          (uint64_t)(cz < cube->nz ? cz : cube->nz);
-    uint32_t rshift = nbins <= 256 ? 2u : nbins <= 1024 ? 1u : 0u;
-    size_t lds = 0;
-    for (;; --rshift) {
-      lds = mm_lds_bytes(nvox, nbins, rshift, dev.lds_per_block);
-      if (lds || rshift == 0) break;
+  const uint64_t cell_vox = (uint64_t)(cx < cube->nx ? cx : cube->nx) * (uint64_t)(cy < cube->ny ? cy : cube->ny) *
+                            (uint64_t)(cz < cube->nz ? cz : cube->nz);
+  const int ept = mm_ept(cell_vox);
+  if (ept && register_path_on()) {
+    // histogram replicas: up to 16 per bin within 4096 counters
+    uint32_t rshift = 0;
+    while (rshift < 4 && ((uint32_t)nbins << (rshift + 1)) <= 4096u) ++rshift;
+    const size_t lds = ((size_t)kBins1 + kTrash + ((size_t)nbins << rshift) + kTrash) * 4;
+    MMArgs m;
+    m.base = cube->data;
+    m.nx = cube->nx;
+    m.ny = cube->ny;
+    m.nz = cube->nz;
+    m.cx = cx;
+    m.cy = cy;
+    m.cz = cz;
+    m.nbins = nbins;
+    m.ncx = g.ncx;
+    m.ncy = g.ncy;
+    m.ncells = g.ncells;
+    m.per_xcd = (g.ncells + 7) / 8;
+    m.rshift = rshift;
+    m.pad = 0;
+    m.out = d_cells;
+    m.hists = d_hists;
+    const dim3 grid((uint32_t)(m.per_xcd * 8));
+#define TSA_MM_LAUNCH(DTV, EPTV) \
+  TSA_TRACED("minimap_cells", s, hipLaunchKernelGGL((k_mm_reg<DTV, EPTV>), grid, dim3(kMMBlock), lds, s, m))
+    if (cube->dtype == TSA_F32) {
+      if (ept == 8)
+        TSA_MM_LAUNCH(0, 8);
+      else if (ept == 16)
+        TSA_MM_LAUNCH(0, 16);
+      else
+        TSA_MM_LAUNCH(0, 32);
+    } else {
+      if (ept == 8)
+        TSA_MM_LAUNCH(1, 8);
+      else if (ept == 16)
+        TSA_MM_LAUNCH(1, 16);
+      else
+        TSA_MM_LAUNCH(1, 32);
     }
-    if (lds) {
-      MMArgs m;
-      m.base = cube->data;
-      m.nx = cube->nx;
-      m.ny = cube->ny;
-      m.nz = cube->nz;
-      m.cx = cx;
-      m.cy = cy;
-      m.cz = cz;
-      m.nbins = nbins;
-      m.ncx = g.ncx;
-      m.ncy = g.ncy;
-      m.ncells = g.ncells;
-      m.per_xcd = (g.ncells + 7) / 8;
-      m.rshift = rshift;
-      m.pad = 0;
-      m.out = d_cells;
-      m.hists = d_hists;
-      const dim3 grid((uint32_t)(m.per_xcd * 8));
-      if (cube->dtype == TSA_F32) {
-        if (lds > 65536 && hipFuncSetAttribute((const void*)k_mm_lds<0>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               (int)lds) != hipSuccess)
-          return TSA_EDEVICE;
-        TSA_TRACED("minimap_lds", s, hipLaunchKernelGGL(k_mm_lds<0>, grid, dim3(kMMBlock), lds, s, m));
-      } else {
-        if (lds > 65536 && hipFuncSetAttribute((const void*)k_mm_lds<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               (int)lds) != hipSuccess)
-          return TSA_EDEVICE;
-        TSA_TRACED("minimap_lds", s, hipLaunchKernelGGL(k_mm_lds<1>, grid, dim3(kMMBlock), lds, s, m));
-      }
-      return hipGetLastError() == hipSuccess ? TSA_OK : TSA_EDEVICE;
-    }
+#undef TSA_MM_LAUNCH
+    return hipGetLastError() == hipSuccess ? TSA_OK : TSA_EDEVICE;
   }
   tsa_region* boxes = (tsa_region*)d_ws;
   const size_t off = align256(sizeof(tsa_region) * (size_t)g.ncells);

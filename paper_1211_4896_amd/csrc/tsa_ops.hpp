@@ -275,6 +275,15 @@ TSA_DEV void lds_inc(uint32_t* lds, uint32_t idx) {
   __hip_atomic_fetch_add(lds + idx, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Increment for the lanes where m holds, rare across the wave: the wave skips
+// the LDS instruction entirely when no lane needs it (an exec-masked LDS
+// instruction with no active lane still takes an issue slot).
+TSA_DEV void lds_inc_rare(uint32_t* lds, bool m, uint32_t idx) {
+  if (__ballot(m) != 0ull) {
+    if (m) lds_inc(lds, idx);
+  }
+}
+
 TSA_DEV void lds_zero(uint32_t* lds, uint32_t n) {
   for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) lds[i] = 0u;
 }
@@ -611,8 +620,11 @@ struct Level2Acc {  // keys inside the level-1 bucket: next 12 bits, optional co
   TSA_DEV void operator()(T raw, bool in) {
     const uint32_t key = Elt<DT>::key(raw);
     const bool m = Elt<DT>::valid(raw, in) && (key >> kShift1) == p1;
-    if (m) lds_inc(lds, (key >> kShift2) & 0xFFFu);
-    if (compact) cand_append(m, key, sink);
+    const uint64_t bal = __ballot(m);
+    if (bal != 0ull) {  // rare: most waves skip both the count and the copy
+      if (m) lds_inc(lds, (key >> kShift2) & 0xFFFu);
+      if (compact) cand_append_slow(m, key, bal, sink);
+    }
   }
   TSA_DEV void chunk() {}
   // every wave copies what it still holds (call with every lane active)
@@ -628,7 +640,7 @@ struct Level3Acc {  // keys inside the level-2 bucket: last 8 bits
   template <class T>
   TSA_DEV void operator()(T raw, bool in) {
     const uint32_t key = Elt<DT>::key(raw);
-    if (Elt<DT>::valid(raw, in) && (key >> kShift2) == p2) lds_inc(lds, key & 0xFFu);
+    lds_inc_rare(lds, Elt<DT>::valid(raw, in) && (key >> kShift2) == p2, key & 0xFFu);
   }
   TSA_DEV void chunk() {}
 };
