@@ -194,13 +194,30 @@ struct BShared {
   uint32_t q, tile, last, flag;
   uint64_t u64a, u64b;
   MomShared mom;
-  double mn[kBBlock], mm[kBBlock], mq[kBBlock];
-  uint32_t kmin[kBBlock], kmax[kBBlock];
   uint64_t wsum[16];
   uint32_t found;
   uint32_t sel_digit;
   uint64_t sel_cum, sel_bucket;
 };
+
+// The epilogues' per-thread merge arrays live in the dynamic LDS, past the
+// words epilogue 2 counts into: a tile's counters are flushed before its
+// block can run an epilogue, so the space is free then (this keeps the static
+// LDS small and lets more blocks share a compute unit).
+constexpr uint32_t kEpOffWords = 1024;
+struct EpScratch {
+  double* mn;
+  double* mm;
+  double* mq;
+  uint32_t* kmin;
+  uint32_t* kmax;
+};
+TSA_DEV EpScratch ep_scratch(uint32_t* lds) {
+  double* d = (double*)(lds + kEpOffWords);
+  uint32_t* u = (uint32_t*)(d + 3 * kBBlock);
+  return EpScratch{d, d + kBBlock, d + 2 * kBBlock, u, u + kBBlock};
+}
+constexpr size_t kEpLdsBytes = (size_t)kEpOffWords * 4 + (3 * 8 + 2 * 4) * (size_t)kBBlock;
 
 // Thread 0 waits until *p >= v (bounded); result broadcast to the block.
 TSA_DEV bool block_wait_ge(const uint32_t* p, uint32_t v, uint32_t* err, BShared& sh) {
@@ -231,7 +248,8 @@ TSA_DEV bool block_wait_ge(const uint32_t* p, uint32_t v, uint32_t* err, BShared
 // epilogues (whole block)
 // ---------------------------------------------------------------------------
 template <int DT>
-TSA_DEV void epilogue1(const BArgs& a, uint32_t q, BShared& sh) {
+TSA_DEV void epilogue1(const BArgs& a, uint32_t q, BShared& sh, uint32_t* lds) {
+  const EpScratch ep = ep_scratch(lds);
   const QGeom& g = a.geom[q];
   QState& s = a.st[q];
   tsa_result& R = a.results[q];
@@ -250,27 +268,27 @@ TSA_DEV void epilogue1(const BArgs& a, uint32_t q, BShared& sh) {
       mx = max(mx, p.kmax);
     }
   }
-  sh.mn[t] = n;
-  sh.mm[t] = m;
-  sh.mq[t] = m2;
-  sh.kmin[t] = mn;
-  sh.kmax[t] = mx;
+  ep.mn[t] = n;
+  ep.mm[t] = m;
+  ep.mq[t] = m2;
+  ep.kmin[t] = mn;
+  ep.kmax[t] = mx;
   __syncthreads();
   for (int s2 = bs / 2; s2 > 0; s2 >>= 1) {
     if (t < s2) {
-      double x = sh.mn[t], y = sh.mm[t], z = sh.mq[t];
-      chan_merge_b(x, y, z, sh.mn[t + s2], sh.mm[t + s2], sh.mq[t + s2]);
-      sh.mn[t] = x;
-      sh.mm[t] = y;
-      sh.mq[t] = z;
-      sh.kmin[t] = min(sh.kmin[t], sh.kmin[t + s2]);
-      sh.kmax[t] = max(sh.kmax[t], sh.kmax[t + s2]);
+      double x = ep.mn[t], y = ep.mm[t], z = ep.mq[t];
+      chan_merge_b(x, y, z, ep.mn[t + s2], ep.mm[t + s2], ep.mq[t + s2]);
+      ep.mn[t] = x;
+      ep.mm[t] = y;
+      ep.mq[t] = z;
+      ep.kmin[t] = min(ep.kmin[t], ep.kmin[t + s2]);
+      ep.kmax[t] = max(ep.kmax[t], ep.kmax[t + s2]);
     }
     __syncthreads();
   }
-  const uint64_t cnt = (uint64_t)sh.mn[0];
-  const double mean = sh.mm[0];
-  const uint32_t kmin = sh.kmin[0], kmax = sh.kmax[0];
+  const uint64_t cnt = (uint64_t)ep.mn[0];
+  const double mean = ep.mm[0];
+  const uint32_t kmin = ep.kmin[0], kmax = ep.kmax[0];
   const uint32_t* dig = a.digits + (size_t)q * kBins1;
   bool skip2 = false;
   if (t == 0) {
@@ -295,7 +313,7 @@ TSA_DEV void epilogue1(const BArgs& a, uint32_t q, BShared& sh) {
           R.flags |= TSA_FLAG_HIST_SKIPPED;  // an infinite range has no bins
         s.finished = 1;
       } else {
-        const double q2 = sh.mq[0] > 0.0 ? sh.mq[0] : 0.0;
+        const double q2 = ep.mq[0] > 0.0 ? ep.mq[0] : 0.0;
         R.mean = mean;
         R.m2 = q2;
         R.std = sqrt(q2 / (double)cnt);
@@ -366,21 +384,22 @@ TSA_DEV void epilogue2(const BArgs& a, uint32_t q, BShared& sh, uint32_t* lds) {
   QState& s = a.st[q];
   tsa_result& R = a.results[q];
   const int t = threadIdx.x, bs = blockDim.x;
+  const EpScratch ep = ep_scratch(lds);
   if (!s.skip2) {
     const uint64_t n = s.n;
     if (DT == 0 && s.var_on) {
       const uint64_t tb = a.tile_base[q];
       double x = 0.0;
       for (uint32_t i = t; i < g.ntiles; i += bs) x += (double)a.parts2[tb + i].x + (double)a.parts2[tb + i].y;
-      sh.mm[t] = x;
+      ep.mm[t] = x;
       __syncthreads();
       for (int s2 = bs / 2; s2 > 0; s2 >>= 1) {
-        if (t < s2) sh.mm[t] += sh.mm[t + s2];
+        if (t < s2) ep.mm[t] += ep.mm[t + s2];
         __syncthreads();
       }
       if (t == 0) {
         const double dm = R.mean - (double)s.shift;
-        double m2 = ldexp(sh.mm[0], -2 * s.vscale) - (double)n * dm * dm;
+        double m2 = ldexp(ep.mm[0], -2 * s.vscale) - (double)n * dm * dm;
         if (!(m2 > 0.0)) m2 = 0.0;
         R.m2 = m2;
         R.std = sqrt(m2 / (double)n);
@@ -507,9 +526,9 @@ TSA_DEV void walk_tile(const BArgs& a, const QGeom& g, uint32_t tile, F& f) {
 // ---------------------------------------------------------------------------
 template <int DT, bool VEC, bool NT>
 __global__ __launch_bounds__(kBBlock) void k_batch(BArgs a) {
-  extern __shared__ uint32_t lds[];
+  extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
   __shared__ BShared sh;
-  __shared__ CandShared cs;
+  __shared__ CandSharedN<kBBlock / kWave> cs;
   const int t = threadIdx.x;
   const uint64_t T1 = a.hdr->T1;
   for (;;) {
@@ -570,7 +589,7 @@ __global__ __launch_bounds__(kBBlock) void k_batch(BArgs a) {
         const bool hist_on = s.hist_ok != 0, var_on = DT == 0 && s.var_on != 0;
         BPass2<DT> f{HistOwnAcc{lds, s.lo, s.scale, a.nbins - 1, a.rshift, (uint32_t)t & ((1u << a.rshift) - 1u)},
                      Level2Acc<DT>{l2, s.prefix >> kShift1, s.compact != 0,
-                                   CandSink{&cs, a.pool + s.cand_base, &s.cand_fill, s.cand_n}},
+                                   cand_sink(cs, a.pool + s.cand_base, &s.cand_fill, s.cand_n)},
                      VarAcc{s.shift, s.vscale}, hist_on, var_on};
         walk_tile<DT, VEC, NT>(a, g, tile, f);
         f.l2.finish();
@@ -634,7 +653,7 @@ __global__ __launch_bounds__(kBBlock) void k_batch(BArgs a) {
     __syncthreads();
     if (sh.last) {
       if (phase == 1)
-        epilogue1<DT>(a, q, sh);
+        epilogue1<DT>(a, q, sh, lds);
       else if (phase == 2)
         epilogue2<DT>(a, q, sh, lds);
       else
@@ -864,7 +883,8 @@ static int enqueue_region_batch(const tsa_cube* cube, const tsa_region* d_region
   a.pool = (uint32_t*)(ws + L.pool);
   const size_t lds1 = ((size_t)kBins1 + kTrash) * 4;
   const size_t lds2 = (((size_t)nbins << a.rshift) + kTrash + kBins2) * 4;
-  const size_t lds = lds1 > lds2 ? lds1 : lds2;
+  size_t lds = lds1 > lds2 ? lds1 : lds2;
+  if (lds < kEpLdsBytes) lds = kEpLdsBytes;
   bfill(a.hdr, sizeof(BatchHdr) / 4, s);
   bfill(a.digits, (size_t)kBins1 * nq, s);
   bfill(d_hists, (size_t)nbins * nq * 2, s);

@@ -66,7 +66,7 @@ __global__ __launch_bounds__(1024) void k_level2(Geom g, SelState* __restrict__ 
   lds_zero(lds, kBins2);
   cand_init(cs);
   __syncthreads();
-  Level2Acc<DT> a{lds, st->prefix >> kShift1, st->compact != 0, CandSink{&cs, cand, &st->ncand, st->cand_cap}};
+  Level2Acc<DT> a{lds, st->prefix >> kShift1, st->compact != 0, cand_sink(cs, cand, &st->ncand, st->cand_cap)};
   walk<DT, VEC, kUnroll, NT>(g, a);
   a.finish();
   __syncthreads();
@@ -389,7 +389,7 @@ __global__ __launch_bounds__(1024) void k_mlevel2(Geom g, const SelState* __rest
   int32_t mi;
   median_of_state<DT>(med, mf, mi);
   AbsDev<DT, Level2Acc<0>> a{
-      Level2Acc<0>{lds, st->prefix >> kShift1, st->compact != 0, CandSink{&cs, cand, &st->ncand, st->cand_cap}}, mf,
+      Level2Acc<0>{lds, st->prefix >> kShift1, st->compact != 0, cand_sink(cs, cand, &st->ncand, st->cand_cap)}, mf,
       mi};
   walk<DT, VEC, kUnroll, NT>(g, a);
   a.inner.finish();
@@ -549,7 +549,7 @@ __global__ __launch_bounds__(1024) void k_pass_b(Geom g, int32_t nbins, uint32_t
   __syncthreads();
   PassB<DT> b{HistOwnAcc{lds, st->lo, st->scale, nbins - 1, rshift, threadIdx.x & ((1u << rshift) - 1u)},
               Level2Acc<DT>{l2, sel_on ? (st->prefix >> kShift1) : 0xFFFFFFFFu, sel_on && st->compact != 0,
-                            CandSink{&cs, cand, &st->ncand, st->cand_cap}},
+                            cand_sink(cs, cand, &st->ncand, st->cand_cap)},
               VarAcc{st->shift, st->vscale}, hist_on, var_on};
   walk<DT, VEC, kUnroll, NT>(g, b);
   b.l2.finish();
@@ -602,7 +602,7 @@ __global__ __launch_bounds__(1024) void k_pass_b16(Geom g, int32_t nbins, uint32
   __syncthreads();
   PassB16<DT> b{Hist16Acc{lds, st->lo, st->hi, st->scale, nbins - 1, 0, nbins, counts, epoch, 0u, true, 0u, 0u},
                 Level2Acc<DT>{l2, sel_on ? (st->prefix >> kShift1) : 0xFFFFFFFFu, sel_on && st->compact != 0,
-                              CandSink{&cs, cand, &st->ncand, st->cand_cap}},
+                              cand_sink(cs, cand, &st->ncand, st->cand_cap)},
                 VarAcc{st->shift, st->vscale}, hist_on, var_on};
   walk<DT, VEC, kUnroll, NT>(g, b);
   b.l2.finish();

@@ -542,21 +542,31 @@ struct Digit1Acc {  // top 12 key bits of every valid element
 constexpr uint32_t kWaveStage = 128;  // staged keys per wave
 constexpr int kMaxWaves = 16;
 
-struct CandShared {
-  uint32_t buf[kMaxWaves][kWaveStage];
+// Staging of a block of NW waves.
+template <int NW>
+struct CandSharedN {
+  uint32_t buf[NW][kWaveStage];
   // written by one lane, read by all: volatile, so no lane reuses a stale load
-  volatile uint32_t fill[kMaxWaves];
+  volatile uint32_t fill[NW];
 };
+using CandShared = CandSharedN<kMaxWaves>;
 
 struct CandSink {
-  CandShared* cs;
+  uint32_t* buf;          // kWaveStage staged keys per wave
+  volatile uint32_t* fill;  // one fill word per wave
   uint32_t* list;     // global list
   uint32_t* counter;  // global fill counter
   uint32_t cap;       // global capacity
 };
 
+template <int NW>
+TSA_DEV CandSink cand_sink(CandSharedN<NW>& cs, uint32_t* list, uint32_t* counter, uint32_t cap) {
+  return CandSink{&cs.buf[0][0], cs.fill, list, counter, cap};
+}
+
 // Each wave clears its own fill word (before its first append).
-TSA_DEV void cand_init(CandShared& cs) {
+template <int NW>
+TSA_DEV void cand_init(CandSharedN<NW>& cs) {
   if (threadIdx.x % kWave == 0) cs.fill[threadIdx.x / kWave] = 0u;
   __builtin_amdgcn_wave_barrier();
 }
@@ -572,7 +582,7 @@ TSA_DEV void cand_copy_out(const CandSink& k, uint32_t fill) {
   if (lane == leader) g = atomicAdd(k.counter, fill);
   g = __shfl(g, leader);
   for (uint32_t i = rank; i < fill; i += na)
-    if (g + i < k.cap) k.list[g + i] = k.cs->buf[w][i];
+    if (g + i < k.cap) k.list[g + i] = k.buf[w * kWaveStage + i];
   __builtin_amdgcn_wave_barrier();
 }
 
@@ -582,16 +592,16 @@ TSA_DEV void cand_copy_out(const CandSink& k, uint32_t fill) {
 TSA_DEV void cand_append_slow(bool m, uint32_t key, uint64_t bal, const CandSink& k) {
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const uint32_t n = (uint32_t)__popcll(bal);
-  uint32_t fill = k.cs->fill[w];
+  uint32_t fill = k.fill[w];
   if (fill + n > kWaveStage) {
     cand_copy_out(k, fill);
     fill = 0;
   }
   const uint32_t off = (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
-  if (m) k.cs->buf[w][fill + off] = key;
+  if (m) k.buf[w * kWaveStage + fill + off] = key;
   const uint64_t act = __ballot(true);
   __builtin_amdgcn_wave_barrier();
-  if (lane == __ffsll((unsigned long long)act) - 1) k.cs->fill[w] = fill + n;
+  if (lane == __ffsll((unsigned long long)act) - 1) k.fill[w] = fill + n;
   __builtin_amdgcn_wave_barrier();
 }
 
@@ -603,10 +613,10 @@ TSA_DEV void cand_append(bool m, uint32_t key, const CandSink& k) {
 // Whole wave (all lanes active): copy out what is still staged.
 TSA_DEV void cand_finish(const CandSink& k) {
   const int w = threadIdx.x / kWave;
-  const uint32_t fill = k.cs->fill[w];
+  const uint32_t fill = k.fill[w];
   if (fill) cand_copy_out(k, fill);
   __builtin_amdgcn_wave_barrier();
-  if (threadIdx.x % kWave == 0) k.cs->fill[w] = 0u;
+  if (threadIdx.x % kWave == 0) k.fill[w] = 0u;
   __builtin_amdgcn_wave_barrier();
 }
 
