@@ -214,7 +214,7 @@ def main():
     if not args.no_minimap:
         line["minimap"] = _minimap_bench(tsa, torch, api, lib, dev, sh, args.region_reps)
     if not args.no_spectrum:
-        line["spectrum"] = _spectrum_bench(tsa, torch, np, api, lib, dev, sh, args.region_reps)
+        line["spectrum"] = _spectrum_bench(tsa, torch, np, synth, api, lib, dev, sh, args.region_reps)
     del dev, ws
     torch.cuda.empty_cache()
     if not args.no_region:
@@ -344,7 +344,7 @@ def _minimap_bench(tsa, torch, api, lib, dev, sh, reps: int) -> dict:
     (the partition size of the paper's sigma-clipping example), each with
     moments + 64-bin histogram over its own [min,max] + median, then the
     local 3-sigma counts."""
-    cell, nbins, k = (30, 30, 30), 64, 3.0
+    cell, nbins, k = MINIMAP_CELL, MINIMAP_NBINS, MINIMAP_K
     c = tsa.cube_of(dev)
     cp = ctypes.byref(c)
     ncells = int(api.tsa_minimap_cells(cp, *cell))
@@ -403,19 +403,18 @@ def _minimap_bench(tsa, torch, api, lib, dev, sh, reps: int) -> dict:
             "status_errors": int((res["status"] != 0).sum()), "above_total": int(above.sum().item())}
 
 
-def _spectrum_bench(tsa, torch, np, api, lib, dev, sh, reps: int) -> dict:
+SPECTRUM_RAYS, SPECTRUM_SAMPLES, SPECTRUM_SEED = 16384, 2560, 4404
+MINIMAP_CELL, MINIMAP_NBINS, MINIMAP_K = (30, 30, 30), 64, 3.0
+
+
+def _spectrum_bench(tsa, torch, np, synth, api, lib, dev, sh, reps: int) -> dict:
     """The 3-D spectrum tool over the resident cube: 16384 lines of sight
     entering through the z = 0 face at seeded random points, directions within
     45 degrees of the frequency axis, 0.5-voxel steps, 2560 trilinear samples
     each."""
-    nrays, nsamples, step = 16384, 2560, 0.5
+    nrays, nsamples = SPECTRUM_RAYS, SPECTRUM_SAMPLES
     c = tsa.cube_of(dev)
-    rng = np.random.default_rng(4404)
-    o = np.stack([rng.uniform(0, c.nx - 1, nrays), rng.uniform(0, c.ny - 1, nrays), np.zeros(nrays)], axis=1)
-    th = np.arccos(rng.uniform(np.cos(np.pi / 4), 1.0, nrays))
-    ph = rng.uniform(0, 2 * np.pi, nrays)
-    d = np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)], axis=1) * step
-    rays = torch.from_numpy(np.concatenate([o, d], axis=1)).to(dev.device)
+    rays = torch.from_numpy(synth.sight_lines(nrays, (c.nx, c.ny, c.nz), SPECTRUM_SEED)).to(dev.device)
     out = torch.empty((nrays, nsamples), dtype=torch.float64, device=dev.device)
 
     def run():

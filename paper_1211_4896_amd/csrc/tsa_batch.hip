@@ -484,7 +484,7 @@ TSA_DEV void epilogue3(const BArgs& a, uint32_t q, BShared& sh) {
 // ---------------------------------------------------------------------------
 template <int DT>
 struct BPass1 {
-  MomAcc<DT> mom;
+  MomAcc<DT, false> mom;  // the count is the digit histogram's total
   Digit1Acc<DT> d1;
   template <class T>
   TSA_DEV void operator()(T raw, bool in) {
@@ -569,8 +569,12 @@ __global__ __launch_bounds__(kBBlock) void k_batch(BArgs a) {
     if (phase == 1) {
       lds_zero(lds, kBins1 + kTrash);
       __syncthreads();
-      BPass1<DT> f{MomAcc<DT>{}, Digit1Acc<DT>{lds, 0u, 0u}};
+      BPass1<DT> f{MomAcc<DT, false>{}, Digit1Acc<DT>{lds, 0u, 0u}};
       walk_tile<DT, VEC, NT>(a, g, tile, f);
+      __syncthreads();
+      uint32_t c = 0;  // every valid value incremented one first-digit counter
+      for (int b = t; b < kBins1; b += kBBlock) c += lds[b];
+      f.mom.cnt = c;
       block_store_partial(f.mom, sh.mom, a.parts1 + a.tile_base[q] + tile);
       __syncthreads();
       uint32_t* dig = a.digits + (size_t)q * kBins1;

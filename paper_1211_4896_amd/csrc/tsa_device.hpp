@@ -112,6 +112,14 @@ TSA_DEV void fast_two_sum(float a, float b, float& s, float& e) {
   float z = s - a;
   e = b - z;
 }
+// Sum of two non-negative floats with its exact rounding error: Fast2Sum with
+// the larger operand first (for a, b >= 0 the larger value is the larger
+// magnitude), one operation cheaper than TwoSum and the same (s, e).
+TSA_DEV void two_sum_nonneg(float a, float b, float& s, float& e) {
+  const float big = fmaxf(a, b), small = fminf(a, b);
+  s = a + b;
+  e = small - (s - big);
+}
 // Double-word + double-word (Joldes, Muller & Popescu 2017, "AccurateDWPlusDW").
 TSA_DEV void dw_add(float& ah, float& al, float bh, float bl) {
   float sh, sl, th, tl, vh, vl;

@@ -442,7 +442,7 @@ __global__ void k_mad_finish(const SelState* __restrict__ med, const SelState* _
 // ---------------------------------------------------------------------------
 template <int DT>
 struct PassA {
-  MomAcc<DT> mom;
+  MomAcc<DT, false> mom;  // the count is the digit histogram's total
   Digit1Acc<DT> d1;
   template <class T>
   TSA_DEV void operator()(T raw, bool in) {
@@ -459,8 +459,14 @@ __global__ __launch_bounds__(1024) void k_pass_a(Geom g, uint32_t rshift, Partia
   __shared__ MomShared sm;
   lds_zero(lds, ((uint32_t)kBins1 << rshift) + kTrash);
   __syncthreads();
-  PassA<DT> a{MomAcc<DT>{}, Digit1Acc<DT>{lds, rshift, threadIdx.x & ((1u << rshift) - 1u)}};
+  PassA<DT> a{MomAcc<DT, false>{}, Digit1Acc<DT>{lds, rshift, threadIdx.x & ((1u << rshift) - 1u)}};
   walk<DT, VEC, kUnroll, NT>(g, a);
+  // every valid value incremented one first-digit counter: the block's count
+  // is their total (each lane adds a strided share; the partial sums them)
+  __syncthreads();
+  uint32_t c = 0;
+  for (uint32_t i = threadIdx.x; i < ((uint32_t)kBins1 << rshift); i += blockDim.x) c += lds[i];
+  a.mom.cnt = c;
   block_store_partial(a.mom, sm, parts + blockIdx.x);
   __syncthreads();
   lds_flush(lds, kBins1, rshift, hist1);

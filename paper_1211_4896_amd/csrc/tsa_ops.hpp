@@ -34,11 +34,13 @@ struct Elt<1> {
 // float32: each lane keeps sum x and sum x^2 as an unevaluated float pair
 // (hi + lo).  Every addition is split exactly by TwoSum; the rounding error
 // goes to lo.  x^2 is split exactly by an FMA.  NaN and masked lanes add 0.
-template <int DT>
+// COUNT = false: the caller supplies the count (a pass that also builds the
+// first-digit histogram of the valid values has it as the histogram's total).
+template <int DT, bool COUNT = true>
 struct MomAcc;
 
-template <>
-struct MomAcc<0> {
+template <bool COUNT>
+struct MomAcc<0, COUNT> {
   float sh = 0.f, sl = 0.f, qh = 0.f, ql = 0.f;
   uint32_t kmin = 0xFFFFFFFFu, kmax = 0u, cnt = 0u;
   TSA_DEV void operator()(float x, bool in) {
@@ -51,24 +53,26 @@ struct MomAcc<0> {
     const float p = v * v;
     const float pe = __builtin_fmaf(v, v, -p);
     float q, eq;
-    two_sum(qh, p, q, eq);
+    two_sum_nonneg(qh, p, q, eq);  // qh, p >= 0
     qh = q;
     ql += eq + pe;
     const uint32_t k = Elt<0>::key(x);
     kmin = min(kmin, ok ? k : 0xFFFFFFFFu);
     kmax = max(kmax, ok ? k : 0u);
+    if constexpr (COUNT) {
 #if TSA_BALLOT_COUNT
-    cnt += (uint32_t)__popcll(__ballot(ok));  // wave total, kept uniform (scalar unit)
+      cnt += (uint32_t)__popcll(__ballot(ok));  // wave total, kept uniform (scalar unit)
 #else
-    cnt += ok ? 1u : 0u;
+      cnt += ok ? 1u : 0u;
 #endif
+    }
   }
   TSA_DEV void chunk() {}
 };
 
 // int16: exact integer sums (|x| <= 32768, x^2 <= 2^30).
-template <>
-struct MomAcc<1> {
+template <bool COUNT>
+struct MomAcc<1, COUNT> {
   int64_t s = 0;
   uint64_t q = 0;
   uint32_t kmin = 0xFFFFFFFFu, kmax = 0u, cnt = 0u;
@@ -79,7 +83,7 @@ struct MomAcc<1> {
     const uint32_t k = key_i16(x);
     kmin = min(kmin, in ? k : 0xFFFFFFFFu);
     kmax = max(kmax, in ? k : 0u);
-    cnt += in ? 1u : 0u;
+    if constexpr (COUNT) cnt += in ? 1u : 0u;
   }
   TSA_DEV void chunk() {}
 };
@@ -93,7 +97,8 @@ struct alignas(16) MomShared {
   uint64_t cnt[16];
 };
 
-TSA_DEV void block_store_partial(MomAcc<0>& a, MomShared& sm, Partial* out) {
+template <bool COUNT>
+TSA_DEV void block_store_partial(MomAcc<0, COUNT>& a, MomShared& sm, Partial* out) {
   float h, l;
   two_sum(a.sh, a.sl, h, l);
   a.sh = h;
@@ -151,7 +156,8 @@ TSA_DEV void block_store_partial(MomAcc<0>& a, MomShared& sm, Partial* out) {
   }
 }
 
-TSA_DEV void block_store_partial(MomAcc<1>& a, MomShared& sm, Partial* out) {
+template <bool COUNT>
+TSA_DEV void block_store_partial(MomAcc<1, COUNT>& a, MomShared& sm, Partial* out) {
   const int64_t s = wave_sum_i64(a.s);
   const uint64_t q = wave_sum_u64(a.q);
   const uint32_t kmin = wave_min_u32(a.kmin), kmax = wave_max_u32(a.kmax);
@@ -203,7 +209,7 @@ struct VarAcc {
     const float p = d * d;
     const float pe = __builtin_fmaf(d, d, -p);
     float q, eq;
-    two_sum(qh, p, q, eq);
+    two_sum_nonneg(qh, p, q, eq);  // qh, p >= 0
     qh = q;
     ql += eq + __builtin_fmaf(2.0f * d, e, pe);
   }

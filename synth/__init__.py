@@ -140,6 +140,19 @@ def regions(nq: int, dims, seed: int, edge_lo: int = 8, edge_hi: int = 512) -> n
     return out
 
 
+def sight_lines(nrays: int, dims, seed: int, step: float = 0.5, max_angle_deg: float = 45.0) -> np.ndarray:
+    """Rays for the spectrum tool as float64[nrays, 6] = origin (x, y, z) and
+    step vector: origins uniform on the z = 0 face, directions uniform over
+    the cap within max_angle of +z, step length `step` voxels."""
+    rng = np.random.default_rng(seed)
+    nx, ny, _ = dims
+    o = np.stack([rng.uniform(0, nx - 1, nrays), rng.uniform(0, ny - 1, nrays), np.zeros(nrays)], axis=1)
+    th = np.arccos(rng.uniform(np.cos(np.radians(max_angle_deg)), 1.0, nrays))
+    ph = rng.uniform(0, 2 * np.pi, nrays)
+    d = np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)], axis=1) * step
+    return np.concatenate([o, d], axis=1)
+
+
 def key_order_values(rng: np.random.Generator, n: int) -> np.ndarray:
     """Adversarial float32 values: +-0, denormals, +-inf, ties, NaN."""
     pool = np.array([0.0, -0.0, 1e-45, -1e-45, 1.17e-38, -3.4e38, 3.4e38, np.inf, -np.inf, 1.0, -1.0,

@@ -66,3 +66,34 @@ def check_hist(got_counts, got_outl, want_counts, want_outl, what: str = ""):
     assert np.array_equal(gc, want_counts), (what, "counts differ at", np.nonzero(gc != want_counts)[0][:10])
     if got_outl is not None:
         assert np.array_equal(as_u64(got_outl), want_outl), (what, as_u64(got_outl), want_outl)
+
+
+def check_sigma_counts(host, got, cell, k, what="", cells=None):
+    """Local k-sigma counts against the oracle.  The GPU's cell moments differ
+    from the oracle's within the tolerances above, so its threshold may move
+    by that much: each count must lie between the oracle's counts at the
+    threshold pushed up and down by the tolerance (equal unless a voxel sits
+    that close to it).  cells: indices to check (default all).  Returns how
+    many counts equal the oracle's exactly."""
+    import oracle
+    nz, ny, nx = host.shape
+    boxes = oracle.minimap_cells((nx, ny, nz), cell)
+    idx = range(len(boxes)) if cells is None else cells
+    n_equal = 0
+    for i in idx:
+        x0, y0, z0, x1, y1, z1 = (int(v) for v in boxes[i])
+        mo = oracle.moments(host, (x0, y0, z0, x1, y1, z1))
+        if mo["count"] == 0:
+            assert got[i] == 0, (what, i)
+            n_equal += 1
+            continue
+        thr = mo["mean"] + k * mo["std"]
+        rms = math.hypot(mo["mean"], mo["std"])
+        slack = MEAN_REL * abs(mo["mean"]) + MEAN_RMS * rms + abs(k) * STD_REL * mo["std"] + 4e-16 * abs(thr)
+        v = host[z0:z1, y0:y1, x0:x1].astype(np.float64)
+        exact = np.count_nonzero(v > thr)
+        lo = np.count_nonzero(v > thr + slack)
+        hi = np.count_nonzero(v > thr - slack)
+        assert lo <= got[i] <= hi, (what, k, i, (x0, y0, z0, x1, y1, z1), int(got[i]), lo, hi, exact)
+        n_equal += int(got[i] == exact)
+    return n_equal

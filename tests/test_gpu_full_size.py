@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 import synth
-from parity import check_hist, check_median, check_moments
+from parity import check_hist, check_median, check_moments, check_sigma_counts
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -44,3 +44,55 @@ def test_c4_region_batch_sampled():
         check_median(r["median"], want["median"], "f32", f"c4 q{i}")
         assert not want["hist_skipped"]
         check_hist(hists[i], None, want["counts"], None, f"c4 q{i}")
+
+
+def test_c2_minimap_spectrum_rank_sampled():
+    """The benchmark's other workloads on the resident 1024x1024x1280 cube, in
+    the configuration it times: the 30^3 mini-map (52675 cells, 64 bins) and
+    its 3-sigma counts, the spectrum tool's 16384 sight lines x 2560 samples,
+    and the 0.9-quantile and MAD, checked on sampled outputs the oracle
+    computes one by one (quantile and MAD in full)."""
+    import bench
+    spec = synth.SPECS["c2"]
+    _say("case c2 (minimap/spectrum/rank): generating")
+    host, _ = synth.generate(spec)
+    dev = torch.from_numpy(host).to("cuda:0")
+    dims = (spec.nx, spec.ny, spec.nz)
+    cell, nbins, k = bench.MINIMAP_CELL, bench.MINIMAP_NBINS, bench.MINIMAP_K
+    _say("case c2: minimap")
+    res, hists, cells_dev = tsa.minimap(dev, cell, nbins)
+    boxes = oracle.minimap_cells(dims, cell)
+    assert len(res) == len(boxes) == 52675 and np.all(res["status"] == 0)
+    rng = np.random.default_rng(5)
+    pick = sorted(set([0, len(boxes) - 1, 34, 35 * 35 - 1] + list(rng.choice(len(boxes), 12, replace=False))))
+    h = hists.cpu().numpy().view(np.uint64)
+    for i in pick:
+        b = tuple(int(v) for v in boxes[i])
+        want = oracle.stats(host, nbins, b)
+        r = {kk: res[i][kk].item() for kk in res.dtype.names}
+        check_moments(r, want, "f32", f"c2 cell {i}")
+        check_median(r["median"], want["median"], "f32", f"c2 cell {i}")
+        if not want["hist_skipped"]:
+            check_hist(h[i], None, want["counts"], None, f"c2 cell {i}")
+    _say("case c2: 3-sigma counts")
+    above = tsa.sigma_count(dev, cell, cells_dev, k)
+    check_sigma_counts(host, above, cell, k, "c2 sigma", cells=pick)
+    _say("case c2: spectrum")
+    rays = synth.sight_lines(bench.SPECTRUM_RAYS, dims, bench.SPECTRUM_SEED)
+    got = tsa.spectrum(dev, rays, bench.SPECTRUM_SAMPLES).cpu().numpy()
+    rsel = sorted(set([0, len(rays) - 1] + list(rng.choice(len(rays), 14, replace=False))))
+    want = oracle.spectrum(host, rays[rsel, :3], rays[rsel, 3:], bench.SPECTRUM_SAMPLES)
+    g = got[rsel]
+    assert np.array_equal(g, want, equal_nan=True), np.argwhere(~((g == want) | (np.isnan(g) & np.isnan(want))))[:5]
+    _say("case c2: quantile and MAD")
+    wq, n = oracle.quantile(host, 0.9)
+    v, w, cnt = tsa.quantile(dev, 0.9)
+    assert cnt == n and w == 0.0
+    check_median(v, wq, "f32", "c2 q0.9")
+    v2, w2, _ = tsa.quantile(dev, 0.9, digits=2)
+    assert v2 <= wq <= v2 + w2
+    m, mad, cnt = tsa.mad(dev)
+    wm, wmad, wn = oracle.mad(host)
+    assert cnt == wn
+    check_median(m, wm, "f32", "c2 MAD median")
+    check_median(mad, wmad, "f32", "c2 MAD")

@@ -1,5 +1,4 @@
 """Statistical mini-map and local k-sigma counts (Section 4.5) against the oracle, per cell."""
-import math
 import sys
 
 import numpy as np
@@ -7,7 +6,7 @@ import pytest
 
 import oracle
 import synth
-from parity import MEAN_REL, MEAN_RMS, STD_REL, check_hist, check_median, check_moments
+from parity import check_hist, check_median, check_moments, check_sigma_counts
 
 pytestmark = pytest.mark.gpu
 
@@ -46,29 +45,9 @@ def _check_cells(host, res, hists, cell, nbins, what):
 
 
 def _check_sigma(host, got, cell, k, what):
-    """The GPU's cell moments differ from the oracle's within the parity
-    tolerance, so its threshold may move by that much: its count must lie
-    between the oracle's counts at the threshold pushed up and down by the
-    tolerance (these are equal unless a voxel sits that close to it)."""
-    nz, ny, nx = host.shape
-    boxes = oracle.minimap_cells((nx, ny, nz), cell)
-    exact = oracle.sigma_counts(host, cell, k)
-    n_equal = 0
-    for i, b in enumerate(boxes):
-        x0, y0, z0, x1, y1, z1 = (int(v) for v in b)
-        mo = oracle.moments(host, (x0, y0, z0, x1, y1, z1))
-        if mo["count"] == 0:
-            assert got[i] == 0, (what, i)
-            continue
-        thr = mo["mean"] + k * mo["std"]
-        rms = math.hypot(mo["mean"], mo["std"])
-        slack = MEAN_REL * abs(mo["mean"]) + MEAN_RMS * rms + abs(k) * STD_REL * mo["std"] + 4e-16 * abs(thr)
-        v = host[z0:z1, y0:y1, x0:x1].astype(np.float64)
-        lo = np.count_nonzero(v > thr + slack)
-        hi = np.count_nonzero(v > thr - slack)
-        assert lo <= exact[i] <= hi
-        assert lo <= got[i] <= hi, (what, k, i, (x0, y0, z0, x1, y1, z1), int(got[i]), lo, hi, int(exact[i]))
-        n_equal += int(got[i] == exact[i])
+    n_equal = check_sigma_counts(host, got, cell, k, what)
+    # the bracket's centre is the oracle's own count
+    assert n_equal == int(np.count_nonzero(got == oracle.sigma_counts(host, cell, k))), what
     return n_equal
 
 
