@@ -196,6 +196,10 @@ def main():
                 "kernel": dom_name, "avg_ms": round(dom_avg_ms, 4),
                 "bytes_per_launch": per_launch_bytes}
 
+    probe = _read_probe(lib, dev, sh, torch)
+    roofline["achievable_read_GBps"] = probe["GBps"]
+    roofline["frac_of_achievable"] = round(achieved / probe["GBps"], 4)
+
     line = {"metric": METRIC, "value": round(value, 2), "unit": "GVoxel/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -520,6 +524,27 @@ def _serving_bench(torch, np, synth, seconds: float, qps: float) -> dict:
             "errors": errs, "scheduler": st,
             "service_p50_region_ms": pct(svc[kinds == 0], 50), "service_p50_full_ms": pct(svc[kinds != 0], 50),
             "queue_p50_full_ms": pct(qwait[kinds != 0], 50), "single_call_ms": single}
+
+
+def _read_probe(lib, dev, sh, torch, reps: int = 10) -> dict:
+    """Achievable HBM read bandwidth: the passes' load pattern over the same
+    cube with the least possible work (tsa_internal_read_probe)."""
+    lib.tsa_internal_read_probe.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p]
+    lib.tsa_internal_probe_blocks.restype = ctypes.c_int32
+    nbytes = dev.numel() * dev.element_size() // 16 * 16
+    sink = torch.empty(max(1, lib.tsa_internal_probe_blocks()), dtype=torch.int32, device=dev.device)
+    for _ in range(2):
+        lib.tsa_internal_read_probe(dev.data_ptr(), nbytes, sink.data_ptr(), sh)
+    torch.cuda.synchronize()
+    _trace(lib, True, cap=reps + 1)
+    for _ in range(reps):
+        if lib.tsa_internal_read_probe(dev.data_ptr(), nbytes, sink.data_ptr(), sh) != 0:
+            raise RuntimeError("tsa_internal_read_probe failed")
+    torch.cuda.synchronize()
+    k = _trace_read(lib).get("read_probe", [1, 0.0])
+    _trace(lib, False)
+    ms = k[1] / k[0]
+    return {"ms": round(ms, 4), "GBps": round(nbytes / (ms * 1e-3) / 1e9, 1)}
 
 
 def _calib_copy(lib, device, sh, nbytes: int = 1 << 30) -> int:

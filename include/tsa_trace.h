@@ -1,7 +1,8 @@
 /*
  * tsa_trace.h -- measurement support of libtsa.so (not part of the
- * statistics): per-kernel timing with HIP events, and a plain copy kernel
- * whose byte counts calibrate hardware counters.
+ * statistics): per-kernel timing with HIP events, a plain copy kernel whose
+ * byte counts calibrate hardware counters, and a read-only probe that
+ * measures the HBM read bandwidth a streaming kernel can reach.
  */
 #ifndef TSA_TRACE_H
 #define TSA_TRACE_H
@@ -38,6 +39,19 @@ int tsa_trace_read(char* buf, size_t len);
  * Returns TSA_EINVAL on bad arguments.
  */
 int tsa_internal_copy(void* dst, const void* src, size_t bytes, tsa_stream_t stream);
+
+/*
+ * Reads `bytes` (a multiple of 16) from src (device, 16-byte aligned) with the
+ * 16-byte non-temporal loads and the grid shape of the statistics passes
+ * (512 lanes x 2 blocks per compute unit, four loads in flight per lane) and
+ * XOR-folds every 32-bit word: one word per block to d_sink (device, at least
+ * tsa_internal_probe_blocks() words).  The XOR of the d_sink words is the XOR
+ * of the whole buffer.  Returns TSA_EINVAL on bad arguments.
+ */
+int tsa_internal_read_probe(const void* src, size_t bytes, uint32_t* d_sink, tsa_stream_t stream);
+
+/* Number of sink words tsa_internal_read_probe writes on the current device. */
+int32_t tsa_internal_probe_blocks(void);
 
 #ifdef __cplusplus
 }

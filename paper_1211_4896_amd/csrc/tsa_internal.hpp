@@ -21,7 +21,7 @@ constexpr int kMaxBlocks = 8192;      // upper bound of a pass grid (moment part
 
 struct Tuning {
   int block = 512;     // threads per block of the streaming passes
-  int bpc = 2;         // blocks per compute unit
+  int bpc = 0;         // blocks per compute unit (0: each call's own default)
   bool nt = true;      // non-temporal 16-byte loads
   int rep_shift = -1;  // log2 LDS replicas (-1: by bin count)
 };

@@ -656,7 +656,7 @@ static const Tuning& tuning() {
     if (const char* s = getenv("TSA_NT")) x.nt = atoi(s) != 0;
     if (const char* s = getenv("TSA_REP")) x.rep_shift = atoi(s);
     if (x.block != 256 && x.block != 512 && x.block != 1024) x.block = 512;
-    if (x.bpc < 1 || x.bpc > 16) x.bpc = 2;
+    if (x.bpc < 1 || x.bpc > 16) x.bpc = 0;
     if (x.rep_shift < 0 || x.rep_shift > 3) x.rep_shift = -1;
     return x;
   }();
@@ -885,11 +885,16 @@ struct Prep {
   WsLayout L;
   char* ws;
   hipStream_t s;
-  int block, grid;
+  int block, grid, bpc;
 };
 
+// Blocks per compute unit by call (measured on the 1024x1024x1280 float32
+// cube): the fused trio and the moments gain from a third block per CU, the
+// histogram and the radix passes lose.
+constexpr int kBpcStats = 3, kBpcMoments = 3, kBpcHist = 2, kBpcSelect = 2;
+
 static int prepare(const tsa_cube* cube, const tsa_region* region, void* d_ws, size_t ws_bytes,
-                   tsa_stream_t stream, Prep* P) {
+                   tsa_stream_t stream, Prep* P, int bpc_default) {
   int st = check_cube(cube);
   if (st) return st;
   if ((st = region_box(cube, region, &P->box))) return st;
@@ -901,7 +906,8 @@ static int prepare(const tsa_cube* cube, const tsa_region* region, void* d_ws, s
   P->s = (hipStream_t)stream;
   const Tuning& T = tuning();
   P->block = T.block;
-  int maxb = P->dev.cus * T.bpc;
+  P->bpc = T.bpc ? T.bpc : bpc_default;
+  int maxb = P->dev.cus * P->bpc;
   if (maxb > kMaxBlocks) maxb = kMaxBlocks;
   P->grid = pass_grid(P->g, P->vec, P->block, maxb);
   return TSA_OK;
@@ -942,7 +948,7 @@ int run_moments(const tsa_cube* cube, const tsa_region* region, tsa_result* d_ou
                 tsa_stream_t stream) {
   if (!d_out) return TSA_EINVAL;
   Prep P;
-  int st = prepare(cube, region, d_ws, ws_bytes, stream, &P);
+  int st = prepare(cube, region, d_ws, ws_bytes, stream, &P, kBpcMoments);
   if (st) return st;
   Partial* parts = (Partial*)(P.ws + P.L.partials);
   TSA_TRACED("moments", P.s,
@@ -968,7 +974,7 @@ int run_histogram(const tsa_cube* cube, const tsa_region* region, float lo, floa
     scale = sc;
   }
   Prep P;
-  int st = prepare(cube, region, d_ws, ws_bytes, stream, &P);
+  int st = prepare(cube, region, d_ws, ws_bytes, stream, &P, kBpcHist);
   if (st) return st;
   uint64_t* outl = d_outliers ? d_outliers : (uint64_t*)(P.ws + P.L.outl);
   fill32(d_counts, (size_t)nbins * 2, 0u, P.s);
@@ -1009,7 +1015,7 @@ int run_median(const tsa_cube* cube, const tsa_region* region, tsa_result* d_out
                tsa_stream_t stream) {
   if (!d_out) return TSA_EINVAL;
   Prep P;
-  int st = prepare(cube, region, d_ws, ws_bytes, stream, &P);
+  int st = prepare(cube, region, d_ws, ws_bytes, stream, &P, kBpcSelect);
   if (st) return st;
   reset_select(P);
   SelState* stp = (SelState*)(P.ws + P.L.state);
@@ -1035,7 +1041,7 @@ int run_stats(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa
   if (!d_out || !d_counts) return TSA_EINVAL;
   if (nbins < 1 || nbins > 65536) return TSA_EINVAL;
   Prep P;
-  int st = prepare(cube, region, d_ws, ws_bytes, stream, &P);
+  int st = prepare(cube, region, d_ws, ws_bytes, stream, &P, kBpcStats);
   if (st) return st;
   const size_t budget = P.dev.lds_per_block < 65536 ? P.dev.lds_per_block : 65536;
   const bool wide = ((size_t)nbins + kTrash + kBins2) * 4 > budget;
@@ -1062,7 +1068,13 @@ int run_stats(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa
   Partial* parts2 = (Partial*)(P.ws + P.L.partials2);
   int np2 = P.grid;
   if (!wide) {
-    uint32_t rsb = rep_shift_for(nbins, budget - (kBins2 + kTrash) * 4);
+    // replicas only as far as bpc blocks of pass B still share a compute unit
+    // (its static LDS: candidate staging, moment reduction, outliers)
+    const size_t per_block = P.dev.lds_per_block / (size_t)P.bpc;
+    const size_t static_b = sizeof(CandShared) + sizeof(MomShared) + 32 * 4;
+    size_t budget_b = per_block > static_b + (kBins2 + kTrash) * 4 ? per_block - static_b : 0;
+    if (budget_b > budget) budget_b = budget;
+    uint32_t rsb = rep_shift_for(nbins, budget_b > (kBins2 + kTrash) * 4 ? budget_b - (kBins2 + kTrash) * 4 : 0);
     const size_t ldsb = (((size_t)nbins << rsb) + kTrash + kBins2) * 4;
     TSA_TRACED("pass_b", P.s,
       TSA_DISPATCH(cube->dtype, P.vec, tuning().nt,
@@ -1102,7 +1114,7 @@ int run_quantile(const tsa_cube* cube, const tsa_region* region, double q, int32
                  void* d_ws, size_t ws_bytes, tsa_stream_t stream) {
   if (!d_out || !(q >= 0.0 && q <= 1.0) || digits < 1 || digits > 3) return TSA_EINVAL;
   Prep P;
-  int st = prepare(cube, region, d_ws, ws_bytes, stream, &P);
+  int st = prepare(cube, region, d_ws, ws_bytes, stream, &P, kBpcSelect);
   if (st) return st;
   reset_select(P);
   SelState* stp = (SelState*)(P.ws + P.L.state);
@@ -1130,7 +1142,7 @@ int run_mad(const tsa_cube* cube, const tsa_region* region, double* d_out, void*
             tsa_stream_t stream) {
   if (!d_out) return TSA_EINVAL;
   Prep P;
-  int st = prepare(cube, region, d_ws, ws_bytes, stream, &P);
+  int st = prepare(cube, region, d_ws, ws_bytes, stream, &P, kBpcSelect);
   if (st) return st;
   reset_select(P);
   SelState* med = (SelState*)(P.ws + P.L.state);

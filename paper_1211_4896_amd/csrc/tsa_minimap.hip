@@ -323,11 +323,17 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
   }
   __syncthreads();  // counters cleared
   // moments, min/max keys and the first key digit
-  MomAcc<0> mom;
+  MomAcc<0, false> mom;  // the count is the first-digit histogram's total
 #pragma unroll
   for (int j = 0; j < EPT; ++j) {
     mom(x[j], true);
     if (x[j] == x[j]) lds_inc(dig, key_f32(__float_as_uint(x[j])) >> kShift1);
+  }
+  __syncthreads();
+  {
+    uint32_t c = 0;
+    for (uint32_t i = t; i < kBins1; i += kMMBlock) c += dig[i];
+    mom.cnt = c;
   }
   block_store_partial(mom, sh.mom, &sh.part);  // ends with thread 0 writing sh.part
   __syncthreads();

@@ -132,6 +132,35 @@ int tsa_trace_read(char* buf, size_t len) {
 }  // extern "C"
 
 namespace tsa {
+// Read-only bandwidth probe: the statistics passes' load pattern with the
+// least possible work per element.
+__global__ __launch_bounds__(512) void k_read_probe(const uint4* __restrict__ src, uint64_t n,
+                                                    uint32_t* __restrict__ sink) {
+  __shared__ uint32_t red[8];
+  constexpr int U = 4;
+  const uint64_t chunk = (uint64_t)blockDim.x * U, stride = chunk * gridDim.x;
+  uint32_t acc = 0;
+  for (uint64_t cb = (uint64_t)blockIdx.x * chunk; cb < n; cb += stride) {
+    uint4 r[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint64_t i = cb + (uint64_t)u * blockDim.x + threadIdx.x;
+      r[u] = i < n ? load16<true>(src + i) : make_uint4(0u, 0u, 0u, 0u);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc ^= r[u].x ^ r[u].y ^ r[u].z ^ r[u].w;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc ^= (uint32_t)__shfl_xor(acc, o);
+  if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t x = 0;
+    for (int w = 0; w < (int)(blockDim.x / 64); ++w) x ^= red[w];
+    sink[blockIdx.x] = x;
+  }
+}
+
 __global__ void k_copy16(const uint4* __restrict__ src, uint4* __restrict__ dst, uint64_t n) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
     dst[i] = src[i];
@@ -147,6 +176,23 @@ int tsa_internal_copy(void* dst, const void* src, size_t bytes, tsa_stream_t str
   hipStream_t s = (hipStream_t)stream;
   trace_begin("copy", s);
   hipLaunchKernelGGL(k_copy16, dim3(2048), dim3(512), 0, s, (const uint4*)src, (uint4*)dst, n);
+  trace_end(s);
+  return hipGetLastError() == hipSuccess ? TSA_OK : TSA_EDEVICE;
+}
+
+int32_t tsa_internal_probe_blocks(void) {
+  DevInfo dev;
+  if (device_info(&dev) != TSA_OK) return 0;
+  return dev.cus * 2;
+}
+
+int tsa_internal_read_probe(const void* src, size_t bytes, uint32_t* d_sink, tsa_stream_t stream) {
+  if (!src || !d_sink || bytes % 16 || (uintptr_t)src % 16) return TSA_EINVAL;
+  const int32_t blocks = tsa_internal_probe_blocks();
+  if (blocks < 1) return TSA_EDEVICE;
+  hipStream_t s = (hipStream_t)stream;
+  trace_begin("read_probe", s);
+  hipLaunchKernelGGL(k_read_probe, dim3(blocks), dim3(512), 0, s, (const uint4*)src, (uint64_t)(bytes / 16), d_sink);
   trace_end(s);
   return hipGetLastError() == hipSuccess ? TSA_OK : TSA_EDEVICE;
 }

@@ -235,3 +235,23 @@ def test_c2_full_size():
     assert res["nan_count"] == nan
     gm = tsa.median(dev)
     check_median(gm["median"], want["median"], "f32", "c2 tsa_median")
+
+
+def test_read_probe_sees_every_word():
+    """The bandwidth probe reads the whole buffer: the XOR of its per-block
+    words is the XOR of every 32-bit word (a ragged tail of vectors included)."""
+    import ctypes
+    rng = np.random.default_rng(12)
+    host = rng.integers(0, 2**32, 3 * 1024 * 1024 + 4 * 37, dtype=np.uint64).astype(np.uint32)
+    dev = torch.from_numpy(host.view(np.int32)).to("cuda:0")
+    lib = tsa.capi().lib
+    lib.tsa_internal_read_probe.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p]
+    lib.tsa_internal_probe_blocks.restype = ctypes.c_int32
+    nb = lib.tsa_internal_probe_blocks()
+    assert nb > 0
+    sink = torch.empty(nb, dtype=torch.int32, device="cuda:0")
+    assert lib.tsa_internal_read_probe(dev.data_ptr(), host.nbytes, sink.data_ptr(), None) == 0
+    assert lib.tsa_internal_read_probe(dev.data_ptr(), 12, sink.data_ptr(), None) == tsa.TSA_EINVAL
+    torch.cuda.synchronize()
+    got = np.bitwise_xor.reduce(sink.cpu().numpy().view(np.uint32))
+    assert got == np.bitwise_xor.reduce(host)
