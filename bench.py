@@ -100,9 +100,21 @@ def _cpu_baseline(host, nbins: int, target_s: float = 12.0) -> dict:
     oracle.stats(sample, nbins)
     dt = time.perf_counter() - t0
     nvox = nz * plane
+    # the three statistics one by one on the same sample
+    parts = {}
+    t0 = time.perf_counter()
+    mo = oracle.moments(sample)
+    parts["moments_s"] = round(time.perf_counter() - t0, 3)
+    t0 = time.perf_counter()
+    oracle.histogram(sample, float(mo["min"]), float(mo["max"]), nbins)
+    parts["histogram_s"] = round(time.perf_counter() - t0, 3)
+    t0 = time.perf_counter()
+    oracle.median(sample)
+    parts["median_s"] = round(time.perf_counter() - t0, 3)
     return {"value": round(nvox / dt / 1e9, 6), "unit": "GVoxel/s", "cores": 1, "kind": "oracle",
             "sample": f"first {nz} of {host.shape[0]} z-slices ({nvox} voxels), moments + {nbins}-bin "
-                      f"histogram over [min,max] + lower median, {dt:.2f} s"}
+                      f"histogram over [min,max] + lower median, {dt:.2f} s",
+            "parts": parts, "host_cpus": os.cpu_count()}
 
 
 def main():
@@ -122,6 +134,8 @@ def main():
     ap.add_argument("--serve-qps", type=float, default=2000.0)
     ap.add_argument("--no-minimap", action="store_true", help="skip the mini-map + k-sigma measurement")
     ap.add_argument("--no-spectrum", action="store_true", help="skip the spectrum-tool measurement")
+    ap.add_argument("--c3", action="store_true",
+                    help="also run the 4096x4096x3072 (206 GB) cube with 65536 bins (about a minute to generate)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this path does not shard)",
@@ -215,6 +229,7 @@ def main():
         line["ops"] = _separate_ops(tsa, api, dev, cp, N, float(res["min"]), float(res["max"]), nbins, sh)
     if args.calib_copy:
         line["calib_copy_bytes"] = _calib_copy(lib, dev.device, sh)
+    line["c1"] = _c1_bench(tsa, torch, synth, lib, sh)
     if not args.no_minimap:
         line["minimap"] = _minimap_bench(tsa, torch, api, lib, dev, sh, args.region_reps)
     if not args.no_spectrum:
@@ -227,7 +242,11 @@ def main():
     if not args.no_serve:
         line["serving"] = _serving_bench(torch, np, synth, args.serve_seconds, args.serve_qps)
         torch.cuda.empty_cache()
-    if not args.no_cpu_baseline:
+    if args.c3:
+        del host
+        line["c3"] = _c3_bench(tsa, torch, np, synth, lib)
+        torch.cuda.empty_cache()
+    if not args.no_cpu_baseline and not args.c3:
         line["cpu_baseline"] = _cpu_baseline(host, nbins)
     print(json.dumps(line), flush=True)
 
@@ -524,6 +543,107 @@ def _serving_bench(torch, np, synth, seconds: float, qps: float) -> dict:
             "errors": errs, "scheduler": st,
             "service_p50_region_ms": pct(svc[kinds == 0], 50), "service_p50_full_ms": pct(svc[kinds != 0], 50),
             "queue_p50_full_ms": pct(qwait[kinds != 0], 50), "single_call_ms": single}
+
+
+def _c1_bench(tsa, torch, synth, lib, sh, reps: int = 20) -> dict:
+    """The small 256^3 cube (67 MB, inside the 256 MB Infinity Cache): tsa_stats
+    with 1024 bins back to back (cache-resident) and after a 1 GiB copy that
+    scrubs the caches before each call."""
+    spec = synth.SPECS["c1"]
+    host, _ = synth.generate(spec)
+    dev = torch.from_numpy(host).to("cuda:0")
+    api = tsa.capi()
+    c = tsa.cube_of(dev)
+    nbins = 1024
+    ws = tsa.workspace(tsa.OP_STATS, dev, None, nbins)
+    out = torch.empty(72, dtype=torch.uint8, device=dev.device)
+    counts = torch.empty(nbins, dtype=torch.int64, device=dev.device)
+    scrub = torch.empty(2 << 30, dtype=torch.uint8, device=dev.device)
+    lib.tsa_internal_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+
+    def run(n, cold):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        tot = 0.0
+        for _ in range(n):
+            if cold:
+                lib.tsa_internal_copy(scrub.data_ptr() + (1 << 30), scrub.data_ptr(), 1 << 30, sh)
+            e0.record()
+            st = api.tsa_stats(ctypes.byref(c), None, nbins, out.data_ptr(), counts.data_ptr(), None,
+                               ws.data_ptr(), ws.numel(), sh)
+            e1.record()
+            if st != 0:
+                raise RuntimeError(f"tsa_stats: {tsa.status_string(st)}")
+            torch.cuda.synchronize()
+            tot += e0.elapsed_time(e1)
+        return tot / n
+
+    run(3, False)
+    hot = run(reps, False)
+    cold = run(reps // 2, True)
+    N = dev.numel()
+    return {"workload": "c1: 256^3 float32 (67 MB) cube; moments + 1024-bin histogram over [min,max] + median",
+            "hot_ms": round(hot, 4), "hot_gvoxel_s": round(N / (hot * 1e-3) / 1e9, 1),
+            "cold_ms": round(cold, 4), "cold_gvoxel_s": round(N / (cold * 1e-3) / 1e9, 1)}
+
+
+def generate_on_device(synth, torch, spec, chunk: int = 32):
+    """A cube generated in z-slabs straight into one device tensor (the host
+    holds one slab at a time).  Returns (tensor, nan count)."""
+    dev = torch.empty((spec.nz, spec.ny, spec.nx), dtype=torch.float32 if spec.dtype == "f32" else torch.int16,
+                      device="cuda:0")
+    nan = 0
+    for z0 in range(0, spec.nz, chunk):
+        z1 = min(spec.nz, z0 + chunk)
+        part, n = synth.generate(spec, z0, z1)
+        dev[z0:z1].copy_(torch.from_numpy(part))
+        nan += n
+    torch.cuda.synchronize()
+    return dev, nan
+
+
+def _c3_bench(tsa, torch, np, synth, lib, reps: int = 5) -> dict:
+    """The 206 GB cube (4096x4096x3072 float32, 20000 sources with log-uniform
+    amplitudes, 0.1% NaN) resident on one GPU: tsa_stats with 65536 bins."""
+    spec = synth.SPECS["c3"]
+    nbins = 65536
+    t0 = time.perf_counter()
+    dev, nan = generate_on_device(synth, torch, spec)
+    t_gen = time.perf_counter() - t0
+    c = tsa.cube_of(dev)
+    cp = ctypes.byref(c)
+    api = tsa.capi()
+    ws = tsa.workspace(tsa.OP_STATS, dev, None, nbins)
+    out = torch.empty(72, dtype=torch.uint8, device=dev.device)
+    counts = torch.empty(nbins, dtype=torch.int64, device=dev.device)
+    outl = torch.empty(2, dtype=torch.int64, device=dev.device)
+    sh = torch.cuda.current_stream().cuda_stream
+
+    def step():
+        st = api.tsa_stats(cp, None, nbins, out.data_ptr(), counts.data_ptr(), outl.data_ptr(), ws.data_ptr(),
+                           ws.numel(), sh)
+        if st != 0:
+            raise RuntimeError(f"tsa_stats: {tsa.status_string(st)}")
+
+    step()
+    torch.cuda.synchronize()
+    _trace(lib, True, cap=reps * 32)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    kern = _trace_read(lib)
+    _trace(lib, False)
+    r = tsa.results_to_numpy(out)[0]
+    N = dev.numel()
+    hist_total = int(counts.sum().item())
+    return {"workload": "c3: 4096x4096x3072 float32 cube (206 GB resident), 20000 sources A log-uniform [3,500], "
+                        "0.1% NaN; moments + 65536-bin histogram over [min,max] + exact median (tsa_stats)",
+            "voxels": N, "ms_per_step": round(ms, 3), "gvoxel_s": round(N / (ms * 1e-3) / 1e9, 1),
+            "kernels_ms": {k: round(v[1] / v[0], 4) for k, v in kern.items()},
+            "count_plus_nan_is_N": int(r["count"]) + int(r["nan_count"]) == N,
+            "nan_count_matches_generator": int(r["nan_count"]) == nan, "hist_total_is_count": hist_total == int(r["count"]),
+            "status": int(r["status"]), "generate_s": round(t_gen, 1)}
 
 
 def _read_probe(lib, dev, sh, torch, reps: int = 10) -> dict:

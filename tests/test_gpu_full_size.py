@@ -1,5 +1,6 @@
 """Full-size workloads in the launch configuration the benchmark times, checked
 on sampled outputs the oracle computes one by one."""
+import os
 import sys
 
 import numpy as np
@@ -96,3 +97,35 @@ def test_c2_minimap_spectrum_rank_sampled():
     assert cnt == wn
     check_median(m, wm, "f32", "c2 MAD median")
     check_median(mad, wmad, "f32", "c2 MAD")
+
+
+@pytest.mark.skipif(os.environ.get("TSA_TEST_C3") != "1",
+                    reason="206 GB cube, about a minute to generate: set TSA_TEST_C3=1 to run")
+def test_c3_full_size_206gb():
+    """The 4096x4096x3072 float32 cube (206 GB) resident on one GPU, 65536
+    bins: whole-cube results checked by invariants that hold at any size
+    (count + nan_count = N, the generator's NaN count, histogram total =
+    count, extremes bound every slab's), and two z-slabs checked against the
+    oracle on every output."""
+    import bench
+    spec = synth.SPECS["c3"]
+    _say("case c3: generating on the device")
+    dev, nan = bench.generate_on_device(synth, torch, spec)
+    N = dev.numel()
+    _say("case c3: gpu stats, 65536 bins")
+    res, counts, outl = tsa.stats(dev, 65536)
+    assert res["status"] == 0
+    assert res["count"] + res["nan_count"] == N and res["nan_count"] == nan
+    assert int(counts.sum().item()) == res["count"] and int(outl.sum().item()) == 0
+    rng = np.random.default_rng(9)
+    for z0 in sorted(rng.choice(spec.nz - 8, 2, replace=False)):
+        z0 = int(z0)
+        box = (0, 0, z0, spec.nx, spec.ny, z0 + 8)
+        _say("case c3: slab", box)
+        host, _ = synth.generate(spec, z0, z0 + 8)
+        want = oracle.stats(host, 65536)
+        got, c, o = tsa.stats(dev, 65536, box)
+        check_moments(got, want, "f32", f"c3 slab {z0}")
+        check_median(got["median"], want["median"], "f32", f"c3 slab {z0}")
+        check_hist(c, o, want["counts"], want["outliers"], f"c3 slab {z0}")
+        assert res["min"] <= want["min"] and want["max"] <= res["max"]
