@@ -540,10 +540,11 @@ __global__ __launch_bounds__(1024) void k_pass_b(Geom g, int32_t nbins, uint32_t
                                                  uint64_t* __restrict__ counts, uint64_t* __restrict__ outl,
                                                  uint64_t* __restrict__ hist2, uint32_t* __restrict__ cand,
                                                  Partial* __restrict__ parts2) {
-  extern __shared__ uint32_t lds[];  // [nbins << rshift] histogram, then [kBins2] level-2 digits
+  // dynamic LDS: [nbins << rshift] histogram, [kBins2] level-2 digits, then the
+  // candidate staging of the block's waves
+  extern __shared__ uint32_t lds[];
   __shared__ uint32_t osm[32];
   __shared__ MomShared sm;
-  __shared__ CandShared cs;
   const uint32_t hsize = ((uint32_t)nbins << rshift) + kTrash;
   uint32_t* l2 = lds + hsize;
   const bool hist_on = st->hist_ok != 0;
@@ -551,11 +552,10 @@ __global__ __launch_bounds__(1024) void k_pass_b(Geom g, int32_t nbins, uint32_t
   const bool var_on = DT == 0 && st->var_on != 0;
   if (!hist_on && !sel_on && !var_on) return;
   lds_zero(lds, hsize + kBins2);
-  cand_init(cs);
+  const CandSink sink = cand_sink_lds(l2 + kBins2, blockDim.x / kWave, cand, &st->ncand, st->cand_cap);
   __syncthreads();
   PassB<DT> b{HistOwnAcc{lds, st->lo, st->scale, nbins - 1, rshift, threadIdx.x & ((1u << rshift) - 1u)},
-              Level2Acc<DT>{l2, sel_on ? (st->prefix >> kShift1) : 0xFFFFFFFFu, sel_on && st->compact != 0,
-                            cand_sink(cs, cand, &st->ncand, st->cand_cap)},
+              Level2Acc<DT>{l2, sel_on ? (st->prefix >> kShift1) : 0xFFFFFFFFu, sel_on && st->compact != 0, sink},
               VarAcc{st->shift, st->vscale}, hist_on, var_on};
   walk<DT, VEC, kUnroll, NT>(g, b);
   b.l2.finish();
@@ -1044,7 +1044,8 @@ int run_stats(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa
   int st = prepare(cube, region, d_ws, ws_bytes, stream, &P, kBpcStats);
   if (st) return st;
   const size_t budget = P.dev.lds_per_block < 65536 ? P.dev.lds_per_block : 65536;
-  const bool wide = ((size_t)nbins + kTrash + kBins2) * 4 > budget;
+  const size_t cand_b = (size_t)(P.block / kWave) * (kWaveStage + 1) * 4;  // pass B's candidate staging
+  const bool wide = ((size_t)nbins + kTrash + kBins2) * 4 + cand_b > budget;
   // 16-bit counters: (nbins+1)/2 words + level-2 digits, plus ~10 KB of static LDS
   const size_t lds16 = ((((size_t)nbins + 1) / 2) + kBins2) * 4;
   if (wide && lds16 + 10240 > P.dev.lds_per_block) return TSA_ENOTSUP;
@@ -1071,11 +1072,12 @@ int run_stats(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa
     // replicas only as far as bpc blocks of pass B still share a compute unit
     // (its static LDS: candidate staging, moment reduction, outliers)
     const size_t per_block = P.dev.lds_per_block / (size_t)P.bpc;
-    const size_t static_b = sizeof(CandShared) + sizeof(MomShared) + 32 * 4;
-    size_t budget_b = per_block > static_b + (kBins2 + kTrash) * 4 ? per_block - static_b : 0;
-    if (budget_b > budget) budget_b = budget;
-    uint32_t rsb = rep_shift_for(nbins, budget_b > (kBins2 + kTrash) * 4 ? budget_b - (kBins2 + kTrash) * 4 : 0);
-    const size_t ldsb = (((size_t)nbins << rsb) + kTrash + kBins2) * 4;
+    // (and within the 64 KB a launch takes without raising its LDS limit)
+    const size_t fixed_b = sizeof(MomShared) + 32 * 4 + cand_b + (kBins2 + kTrash) * 4 + 1024;  // + slack
+    const size_t cap_b = per_block < budget ? per_block : budget;
+    const size_t budget_b = cap_b > fixed_b ? cap_b - fixed_b : 0;
+    uint32_t rsb = rep_shift_for(nbins, budget_b);
+    const size_t ldsb = (((size_t)nbins << rsb) + kTrash + kBins2) * 4 + cand_b;
     TSA_TRACED("pass_b", P.s,
       TSA_DISPATCH(cube->dtype, P.vec, tuning().nt,
                    hipLaunchKernelGGL((k_pass_b<DT, VEC, NT>), dim3(P.grid), dim3(P.block), ldsb, P.s, P.g, nbins,

@@ -577,6 +577,16 @@ TSA_DEV void cand_init(CandSharedN<NW>& cs) {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Staging carved from dynamic LDS: kWaveStage words per wave of the block,
+// then one fill word per wave (cand_lds_words() in all).
+TSA_DEV uint32_t cand_lds_words(uint32_t waves) { return waves * (kWaveStage + 1u); }
+TSA_DEV CandSink cand_sink_lds(uint32_t* base, uint32_t waves, uint32_t* list, uint32_t* counter, uint32_t cap) {
+  volatile uint32_t* fill = base + waves * kWaveStage;
+  if (threadIdx.x % kWave == 0) fill[threadIdx.x / kWave] = 0u;
+  __builtin_amdgcn_wave_barrier();
+  return CandSink{base, fill, list, counter, cap};
+}
+
 // Active lanes of a wave copy its `fill` staged keys out (one global atomic).
 TSA_DEV void cand_copy_out(const CandSink& k, uint32_t fill) {
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
