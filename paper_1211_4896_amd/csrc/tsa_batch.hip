@@ -29,6 +29,10 @@ constexpr uint32_t kDefTileUnits = 16384;  // 16-byte vectors per tile (64K floa
 constexpr uint32_t kDefCandMax = 1u << 20;  // largest first-digit bucket copied out
 constexpr uint32_t kPoolPerQuery = 16384;   // candidate pool keys per query (shared by the batch)
 constexpr int kBBlock = 256;
+#ifndef TSA_BATCH_UNROLL
+#define TSA_BATCH_UNROLL 4
+#endif
+constexpr int kBUnroll = TSA_BATCH_UNROLL;  // 16-byte loads in flight per lane in a tile walk
 constexpr int kMaxQueries = 65536;
 constexpr uint32_t kSpinLimit = 1u << 24;        // polls per wait, at most
 constexpr uint64_t kWaitTicks = 100000000ull * 10;  // 10 s of the 100 MHz wall clock
@@ -517,8 +521,8 @@ TSA_DEV void walk_tile(const BArgs& a, const QGeom& g, uint32_t tile, F& f) {
   const uint32_t nr = min(g.rpt, g.nrows - r0);
   const int64_t epv = VEC ? (DT == 0 ? 4 : 8) : 1;
   const int64_t ys = a.nx / epv, zs = (a.nx / epv) * a.ny;
-  walk_rows<DT, VEC, kUnroll, NT>(a.base, g.v_origin, ys, zs, g.ly, g.ly_m, g.vpr, g.vpr_m, g.head_skip,
-                                  g.last_valid, r0, nr, f);
+  walk_rows<DT, VEC, kBUnroll, NT>(a.base, g.v_origin, ys, zs, g.ly, g.ly_m, g.vpr, g.vpr_m, g.head_skip,
+                                   g.last_valid, r0, nr, f);
 }
 
 // ---------------------------------------------------------------------------

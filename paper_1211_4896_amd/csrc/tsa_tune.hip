@@ -74,7 +74,7 @@ int tsa_tune_region_batch(const tsa_cube* cube, const tsa_region* d_regions, int
     (void)hipEventDestroy(e0);
     return TSA_EDEVICE;
   }
-  const int32_t tiles[] = {16384, 65536, 262144};
+  const int32_t tiles[] = {65536, 262144, 1048576};
   const int32_t bpcs[] = {2, 4, 6, 8};
   float bms = 1e30f;
   tsa_tune bt = {65536, 256, 4, 65536};

@@ -33,6 +33,16 @@ struct Geom {
 
 // Rows [r0, r0 + nr) of a box (row r is y = r % ly, z = r / ly inside the
 // box), flattened over (row, vector) so narrow rows still fill the lanes.
+// Unit li (a vector, or an element on the scalar path) is column li % vpr of
+// tile row li / vpr.  A lane finds its first U units with two divisions by
+// invariant divisors, then steps every unit by bs*U units with constant
+// increments and at most one carry per axis: no division and no 64-bit
+// multiply inside the loop.
+struct RowCursor {
+  uint32_t j, ry, rz;  // column, y and z of the unit inside the box
+  int64_t off;         // its index from the box origin, in units
+};
+
 template <int DT, bool VEC, int U, bool NT, class F>
 TSA_DEV void walk_rows(const void* base, int64_t v_origin, int64_t v_ystride, int64_t v_zstride, uint32_t ly,
                        const Magic& ly_m, uint32_t vpr, const Magic& vpr_m, uint32_t head_skip, uint32_t last_valid,
@@ -41,30 +51,34 @@ TSA_DEV void walk_rows(const void* base, int64_t v_origin, int64_t v_ystride, in
   using T = typename TT::T;
   const uint32_t bs = blockDim.x;
   const uint32_t cnt = nr * vpr;
-  for (uint32_t li0 = 0; li0 < cnt; li0 += bs * U) {
+  if (cnt == 0) return;
+  // the step of bs*U units as (rows, columns), the rows as (planes, y)
+  const uint32_t step = bs * U;
+  const uint32_t dq = mdiv(step, vpr_m), dr = step - dq * vpr;
+  const uint32_t dqz = mdiv(dq, ly_m), dqy = dq - dqz * ly;
+  const int64_t dstep = (int64_t)dqz * v_zstride + (int64_t)dqy * v_ystride + dr;
+  RowCursor c[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const uint32_t li = u * bs + threadIdx.x;
+    const uint32_t lr = mdiv(li, vpr_m);
+    c[u].j = li - lr * vpr;
+    const uint32_t row = r0 + lr;
+    c[u].rz = mdiv(row, ly_m);
+    c[u].ry = row - c[u].rz * ly;
+    c[u].off = (int64_t)c[u].rz * v_zstride + (int64_t)c[u].ry * v_ystride + c[u].j;
+  }
+  for (uint32_t li0 = 0; li0 < cnt; li0 += step) {
     if constexpr (VEC) {
-      const uint4* vb = (const uint4*)base;
+      const uint4* vb = (const uint4*)base + v_origin;
       uint4 r[U];
-      uint32_t jj[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (li0 + u * bs + threadIdx.x < cnt) r[u] = load16<NT>(vb + c[u].off);
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const uint32_t li = li0 + u * bs + threadIdx.x;
-        jj[u] = 0xFFFFFFFFu;
-        if (li < cnt) {
-          const uint32_t lr = mdiv(li, vpr_m);
-          const uint32_t j = li - lr * vpr;
-          const uint32_t row = r0 + lr;
-          const uint32_t rz = mdiv(row, ly_m);
-          const uint32_t ry = row - rz * ly;
-          const int64_t vi = v_origin + (int64_t)rz * v_zstride + (int64_t)ry * v_ystride + j;
-          r[u] = load16<NT>(vb + vi);
-          jj[u] = j;
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (jj[u] != 0xFFFFFFFFu) {
-          const bool first = jj[u] == 0, last = jj[u] == vpr - 1;
+        if (li0 + u * bs + threadIdx.x < cnt) {
+          const bool first = c[u].j == 0, last = c[u].j == vpr - 1;
 #pragma unroll
           for (int e = 0; e < TT::EPV; ++e) {
             const bool in = (!first || (uint32_t)e >= head_skip) && (!last || (uint32_t)e < last_valid);
@@ -73,19 +87,28 @@ TSA_DEV void walk_rows(const void* base, int64_t v_origin, int64_t v_ystride, in
         }
       }
     } else {
-      const T* sb = (const T*)base;
+      const T* sb = (const T*)base + v_origin;
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const uint32_t li = li0 + u * bs + threadIdx.x;
-        if (li < cnt) {
-          const uint32_t lr = mdiv(li, vpr_m);
-          const uint32_t j = li - lr * vpr;
-          const uint32_t row = r0 + lr;
-          const uint32_t rz = mdiv(row, ly_m);
-          const uint32_t ry = row - rz * ly;
-          const int64_t ei = v_origin + (int64_t)rz * v_zstride + (int64_t)ry * v_ystride + j;
-          f(sb[ei], true);
-        }
+      for (int u = 0; u < U; ++u)
+        if (li0 + u * bs + threadIdx.x < cnt) f(sb[c[u].off], true);
+    }
+    // advance every cursor by step units
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      RowCursor& k = c[u];
+      k.j += dr;
+      k.ry += dqy;
+      k.rz += dqz;
+      k.off += dstep;
+      if (k.j >= vpr) {  // carry from the column into the row
+        k.j -= vpr;
+        k.ry += 1;
+        k.off += v_ystride - (int64_t)vpr;
+      }
+      if (k.ry >= ly) {  // carry from y into z (ry < 2 ly here)
+        k.ry -= ly;
+        k.rz += 1;
+        k.off += v_zstride - (int64_t)ly * v_ystride;
       }
     }
     f.chunk();

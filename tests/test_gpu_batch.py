@@ -191,5 +191,5 @@ def test_autotuner_choice_is_used_and_correct():
     boxes = _boxes((128, 96, 64), 123, 31, lo=4, hi=96)
     _say("case batch autotuner")
     best, ms = tsa.tune_region_batch(dev, boxes, 64, reps=1)
-    assert best[0] in (16384, 65536, 262144) and best[2] in (2, 4, 6, 8) and ms > 0
+    assert best[0] in (65536, 262144, 1048576) and best[2] in (2, 4, 6, 8) and ms > 0
     _check_batch(host, dev, boxes, 64, what="tuned")  # tune=None: the remembered choice
