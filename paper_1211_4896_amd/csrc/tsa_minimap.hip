@@ -255,6 +255,7 @@ struct MMArgs {
   int32_t cx, cy, cz, nbins;
   int64_t ncx, ncy, ncells, per_xcd;
   uint32_t rshift, pad;
+  Magic mx_full, mx_edge, my_full, my_edge;  // division by a cell's width / height (full or last cell)
   tsa_result* out;
   uint64_t* hists;
 };
@@ -306,18 +307,39 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
   // 1. every load of the lane in flight at once
   float x[EPT];
   {
-    const Magic mw = dev_magic(w), mh = dev_magic(h);
-    const T* base = (const T*)a.base;
+    // voxel v = t + 1024 j of the cell is (v % w, (v / w) % h, v / (w h)); the
+    // lane divides once, then steps by 1024 voxels with constant increments
+    // and at most one carry per axis (no division in the loop)
     const int64_t plane = a.nx * a.ny;
+    const T* base = (const T*)a.base + (z0 * plane + y0 * a.nx + x0);
+    const Magic mw = w == (uint32_t)a.cx ? a.mx_full : a.mx_edge;
+    const Magic mh = h == (uint32_t)a.cy ? a.my_full : a.my_edge;
+    const uint32_t dq = mdiv((uint32_t)kMMBlock, mw), dr = (uint32_t)kMMBlock - dq * w;
+    const uint32_t dqz = mdiv(dq, mh), dqy = dq - dqz * h;
+    const int64_t dstep = (int64_t)dqz * plane + (int64_t)dqy * a.nx + dr;
+    const uint32_t row0 = mdiv((uint32_t)t, mw);
+    uint32_t lx = (uint32_t)t - row0 * w, lz = mdiv(row0, mh), ly = row0 - lz * h;
+    int64_t off = (int64_t)lz * plane + (int64_t)ly * a.nx + lx;
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
       const uint32_t v = (uint32_t)(j * kMMBlock + t);
-      if (v < nvox) {
-        const uint32_t row = mdiv(v, mw), lx = v - row * w;
-        const uint32_t lz = mdiv(row, mh), ly = row - lz * h;
-        x[j] = (float)base[(z0 + lz) * plane + (y0 + ly) * a.nx + x0 + lx];
-      } else {
+      if (v < nvox)  // slots past the cell never touch memory
+        x[j] = (float)base[off];
+      else
         x[j] = __builtin_nanf("");
+      lx += dr;
+      ly += dqy;
+      lz += dqz;
+      off += dstep;
+      if (lx >= w) {
+        lx -= w;
+        ly += 1;
+        off += a.nx - (int64_t)w;
+      }
+      if (ly >= h) {
+        ly -= h;
+        lz += 1;
+        off += plane - (int64_t)h * a.nx;
       }
     }
   }
@@ -461,9 +483,8 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
 
 // Values per lane needed for a cell of nvox voxels (0: more than the register path holds).
 int mm_ept(uint64_t nvox) {
-  if (nvox <= 8u * kMMBlock) return 8;
-  if (nvox <= 16u * kMMBlock) return 16;
-  if (nvox <= 32u * kMMBlock) return 32;
+  for (int e : {8, 16, 24, 28, 32})
+    if (nvox <= (uint64_t)e * kMMBlock) return e;
   return 0;
 }
 
@@ -515,6 +536,11 @@ int run_minimap(const tsa_cube* cube, int32_t cx, int32_t cy, int32_t cz, int32_
     m.per_xcd = (g.ncells + 7) / 8;
     m.rshift = rshift;
     m.pad = 0;
+    const int64_t ex = cube->nx - (g.ncx - 1) * cx, ey = cube->ny - (g.ncy - 1) * cy;  // last cell's edges
+    m.mx_full = make_magic((uint32_t)(cx < cube->nx ? cx : cube->nx));
+    m.mx_edge = make_magic((uint32_t)ex);
+    m.my_full = make_magic((uint32_t)(cy < cube->ny ? cy : cube->ny));
+    m.my_edge = make_magic((uint32_t)ey);
     m.out = d_cells;
     m.hists = d_hists;
     const dim3 grid((uint32_t)(m.per_xcd * 8));
@@ -525,6 +551,10 @@ int run_minimap(const tsa_cube* cube, int32_t cx, int32_t cy, int32_t cz, int32_
         TSA_MM_LAUNCH(0, 8);
       else if (ept == 16)
         TSA_MM_LAUNCH(0, 16);
+      else if (ept == 24)
+        TSA_MM_LAUNCH(0, 24);
+      else if (ept == 28)
+        TSA_MM_LAUNCH(0, 28);
       else
         TSA_MM_LAUNCH(0, 32);
     } else {
@@ -532,6 +562,10 @@ int run_minimap(const tsa_cube* cube, int32_t cx, int32_t cy, int32_t cz, int32_
         TSA_MM_LAUNCH(1, 8);
       else if (ept == 16)
         TSA_MM_LAUNCH(1, 16);
+      else if (ept == 24)
+        TSA_MM_LAUNCH(1, 24);
+      else if (ept == 28)
+        TSA_MM_LAUNCH(1, 28);
       else
         TSA_MM_LAUNCH(1, 32);
     }

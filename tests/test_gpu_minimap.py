@@ -78,6 +78,15 @@ def test_minimap_ragged_cells_and_chunks():
     _run(host, (4100, 6, 9), 16, (1.0,), "one cell")
 
 
+def test_minimap_register_sizes():
+    """Cells filling each register layout: up to 8, 16, 24, 28 and 32 values per lane."""
+    rng = np.random.default_rng(13)
+    host = (rng.standard_normal((64, 60, 100)) * 3 + 1).astype(np.float32)
+    host[10, 5:9, :] = np.nan
+    for cell in ((16, 16, 16), (32, 16, 30), (40, 25, 20), (30, 30, 30), (32, 32, 32)):
+        _run(host, cell, 16, (2.0,), f"cells {cell}")
+
+
 def test_minimap_scalar_path_unaligned_rows():
     rng = np.random.default_rng(9)
     host = (rng.standard_normal((11, 13, 203)) * 5 + 2).astype(np.float32)  # nx % 4 != 0
