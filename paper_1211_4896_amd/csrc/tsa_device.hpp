@@ -190,7 +190,9 @@ struct SelState {
   double q;           // rank_mode 1: the rank is floor(q (n - 1))
   uint32_t rank_mode; // 0: lower median, 1: quantile q
   uint32_t levels;    // digits to select before stopping (3 = exact)
+  int32_t win0;       // fused path, many bins: first bin of the LDS window
+  uint32_t pad;
 };
-static_assert(sizeof(SelState) == 96, "state layout");
+static_assert(sizeof(SelState) == 104, "state layout");
 
 }  // namespace tsa

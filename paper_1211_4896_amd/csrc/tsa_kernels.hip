@@ -516,6 +516,21 @@ __global__ __launch_bounds__(1024) void k_mid(const Partial* __restrict__ parts,
   }
   __syncthreads();
   select_level(1, hist1, st, dtype, volume, out, false, ssm);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // many bins: pass B counts the kWinBins bins around the median's first-digit
+    // bucket in LDS (where noise-dominated cubes put nearly every value)
+    int32_t w0 = 0;
+    if (st->hist_ok && nbins > (int32_t)kWinBins) {
+      double bm = ((double)(float)value_of_key(st->prefix, dtype) - (double)st->lo) * (double)st->scale;
+      if (!(bm >= 0.0)) bm = 0.0;
+      if (bm > (double)(nbins - 1)) bm = (double)(nbins - 1);
+      w0 = (int32_t)bm - (int32_t)(kWinBins / 2);
+      if (w0 > nbins - (int32_t)kWinBins) w0 = nbins - (int32_t)kWinBins;
+      if (w0 < 0) w0 = 0;
+    }
+    st->win0 = w0;
+  }
 }
 
 template <int DT>
@@ -564,6 +579,59 @@ __global__ __launch_bounds__(1024) void k_pass_b(Geom g, int32_t nbins, uint32_t
   if (sel_on) lds_flush(l2, kBins2, 0, hist2);
   // values lie in their own [min, max]: the outlier counters keep their zeros
 
+  if (var_on) block_store_var(b.var, sm, parts2 + blockIdx.x);
+}
+
+// Pass B with a window of kWinBins 32-bit LDS counters (more bins than fit):
+// one 1024-lane block per compute unit; values outside the window go straight
+// to the global bins.
+template <int DT>
+struct PassBWin {
+  HistWinAcc h;
+  Level2Acc<DT> l2;
+  VarAcc var;
+  bool hist_on, var_on;
+  template <class T>
+  TSA_DEV void operator()(T raw, bool in) {
+    if (hist_on) h(raw, in);
+    l2(raw, in);
+    if constexpr (DT == 0) {
+      if (var_on) var(raw, in);
+    }
+  }
+  TSA_DEV void chunk() {}
+};
+
+template <int DT, bool VEC, bool NT>
+__global__ __launch_bounds__(1024) void k_pass_bwin(Geom g, int32_t nbins, SelState* __restrict__ st,
+                                                    uint64_t* __restrict__ counts, uint64_t* __restrict__ hist2,
+                                                    uint32_t* __restrict__ cand, Partial* __restrict__ parts2) {
+  // dynamic LDS: [kWinBins] window counters, [kBins2] level-2 digits, candidate staging
+  extern __shared__ uint32_t lds[];
+  __shared__ MomShared sm;
+  uint32_t* l2 = lds + kWinBins;
+  const bool hist_on = st->hist_ok != 0;
+  const bool sel_on = st->done == 0;
+  const bool var_on = DT == 0 && st->var_on != 0;
+  if (!hist_on && !sel_on && !var_on) return;
+  lds_zero(lds, kWinBins + kBins2);
+  const CandSink sink = cand_sink_lds(l2 + kBins2, blockDim.x / kWave, cand, &st->ncand, st->cand_cap);
+  __syncthreads();
+  const int32_t w0 = st->win0;
+  PassBWin<DT> b{HistWinAcc{lds, st->lo, st->scale, nbins - 1, w0, counts},
+                 Level2Acc<DT>{l2, sel_on ? (st->prefix >> kShift1) : 0xFFFFFFFFu, sel_on && st->compact != 0, sink},
+                 VarAcc{st->shift, st->vscale}, hist_on, var_on};
+  walk<DT, VEC, kUnroll, NT>(g, b);
+  b.l2.finish();
+  __syncthreads();
+  if (hist_on) {
+    const uint32_t nw = (uint32_t)min((int32_t)kWinBins, nbins - w0);
+    for (uint32_t i = threadIdx.x; i < nw; i += blockDim.x) {
+      const uint32_t c = lds[i];
+      if (c) atomicAdd((unsigned long long*)(counts + w0 + i), (unsigned long long)c);
+    }
+  }
+  if (sel_on) lds_flush(l2, kBins2, 0, hist2);
   if (var_on) block_store_var(b.var, sm, parts2 + blockIdx.x);
 }
 
@@ -944,6 +1012,18 @@ static int launch_pass_b16(const Prep& P, int block, int grid, size_t lds, int32
   return TSA_OK;
 }
 
+template <int DT, bool VEC, bool NT>
+static int launch_pass_bwin(const Prep& P, int block, int grid, size_t lds, int32_t nbins, SelState* stp,
+                            uint64_t* d_counts, uint64_t* h2, uint32_t* cand, Partial* parts2) {
+  if (hipFuncSetAttribute((const void*)k_pass_bwin<DT, VEC, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)lds) != hipSuccess)
+    return TSA_EDEVICE;
+  TSA_TRACED("pass_bwin", P.s,
+             hipLaunchKernelGGL((k_pass_bwin<DT, VEC, NT>), dim3(grid), dim3(block), lds, P.s, P.g, nbins, stp,
+                                d_counts, h2, cand, parts2));
+  return TSA_OK;
+}
+
 int run_moments(const tsa_cube* cube, const tsa_region* region, tsa_result* d_out, void* d_ws, size_t ws_bytes,
                 tsa_stream_t stream) {
   if (!d_out) return TSA_EINVAL;
@@ -1083,11 +1163,24 @@ int run_stats(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa
                    hipLaunchKernelGGL((k_pass_b<DT, VEC, NT>), dim3(P.grid), dim3(P.block), ldsb, P.s, P.g, nbins,
                                       rsb, stp, d_counts, outl, h2, cand, parts2)));
   } else {
-    // one 1024-thread block per compute unit holds the 16-bit counters
+    // one 1024-thread block per compute unit: a window of 32-bit counters when
+    // the device grants the LDS, else 16-bit counters flushed in epochs
     const int blk = 1024;
     int grid = P.dev.cus;
     if (grid > P.grid) grid = P.grid;
     np2 = grid;
+    const size_t lds_win = ((size_t)kWinBins + kBins2 + (blk / kWave) * (kWaveStage + 1)) * 4;
+    if (lds_win + sizeof(MomShared) + 1024 <= P.dev.lds_per_block) {
+      int stw = TSA_OK;
+      TSA_DISPATCH(cube->dtype, P.vec, tuning().nt,
+                   stw = (launch_pass_bwin<DT, VEC, NT>(P, blk, grid, lds_win, nbins, stp, d_counts, h2, cand,
+                                                        parts2)));
+      if (stw) return stw;
+      TSA_TRACED("var_finish", P.s,
+                 hipLaunchKernelGGL(k_var_finish, dim3(1), dim3(1024), 0, P.s, (const Partial*)parts2, np2,
+                                    (const SelState*)stp, d_out));
+      return launch_median_tail(cube, P, d_out, false);
+    }
     const int epv = P.vec ? (cube->dtype == TSA_F32 ? 4 : 8) : 1;
     const int64_t ep = (65535 - 16) / ((int64_t)blk * kUnroll * epv);
     if (ep < 1) return TSA_ENOTSUP;

@@ -357,6 +357,32 @@ struct HistOwnAcc {
   TSA_DEV void chunk() {}
 };
 
+// Histogram over the values' own [min, max] with more bins than LDS holds as
+// 32-bit counters: a window of kWinBins bins [w0, w0 + kWinBins) is counted in
+// LDS, bins outside it directly in the global counters (exact for any data;
+// fast when the window holds most values).  Same bins as HistOwnAcc.
+constexpr uint32_t kWinBins = 32768;
+struct HistWinAcc {
+  uint32_t* lds;
+  float lo, scale;
+  int32_t nbm1, w0;
+  uint64_t* counts;
+  template <class T>
+  TSA_DEV void operator()(T raw, bool in) {
+    const float v = (float)raw;  // exact for int16
+    if (in && v == v) {
+      const float t = (v - lo) * scale;
+      const int32_t b = min((int32_t)t, nbm1);
+      const uint32_t rel = (uint32_t)(b - w0);
+      if (rel < kWinBins)
+        lds_inc(lds, rel);
+      else
+        atomicAdd((unsigned long long*)(counts + b), 1ull);
+    }
+  }
+  TSA_DEV void chunk() {}
+};
+
 // ---- histogram with 16-bit LDS counters (up to 65536 bins) ---------------------
 // Bins [b0, b0+nb) live as 16-bit halves of LDS words; every `epoch` calls of
 // chunk() the block adds its non-zero counters to the global uint64 bins and

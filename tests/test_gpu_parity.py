@@ -255,3 +255,27 @@ def test_read_probe_sees_every_word():
     torch.cuda.synchronize()
     got = np.bitwise_xor.reduce(sink.cpu().numpy().view(np.uint32))
     assert got == np.bitwise_xor.reduce(host)
+
+
+@pytest.mark.parametrize("case", ["spread", "skewed", "int16"])
+def test_stats_many_bins_outside_window(case):
+    """65536 bins over [min, max]: the fused pass counts a 32768-bin window in
+    LDS and the rest in global memory.  Values spread over the whole range
+    (half outside any window), piled at one end, and int16 must all give the
+    oracle's bins."""
+    rng = np.random.default_rng(21)
+    if case == "spread":
+        host = rng.uniform(-1e6, 1e6, (40, 96, 128)).astype(np.float32)
+    elif case == "skewed":
+        host = np.exp(rng.standard_normal((40, 96, 128)) * 3).astype(np.float32)  # long right tail
+        host[3, 4, 5] = np.nan
+    else:
+        host = rng.integers(-32768, 32768, (40, 96, 128)).astype(np.int16)
+    dev = _dev(host)
+    _say("case many bins", case)
+    res, c, o = tsa.stats(dev, 65536)
+    want = oracle.stats(host, 65536)
+    dt = "i16" if host.dtype == np.int16 else "f32"
+    check_moments(res, want, dt, case)
+    check_median(res["median"], want["median"], dt, case)
+    check_hist(c, o, want["counts"], want["outliers"], case)
