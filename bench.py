@@ -134,6 +134,7 @@ def main():
     ap.add_argument("--serve-qps", type=float, default=2000.0)
     ap.add_argument("--no-minimap", action="store_true", help="skip the mini-map + k-sigma measurement")
     ap.add_argument("--no-spectrum", action="store_true", help="skip the spectrum-tool measurement")
+    ap.add_argument("--no-c1", action="store_true", help="skip the 256^3 cache-resident case")
     ap.add_argument("--c3", action="store_true",
                     help="also run the 4096x4096x3072 (206 GB) cube with 65536 bins (about a minute to generate)")
     args = ap.parse_args()
@@ -229,7 +230,8 @@ def main():
         line["ops"] = _separate_ops(tsa, api, dev, cp, N, float(res["min"]), float(res["max"]), nbins, sh)
     if args.calib_copy:
         line["calib_copy_bytes"] = _calib_copy(lib, dev.device, sh)
-    line["c1"] = _c1_bench(tsa, torch, synth, lib, sh)
+    if not args.no_c1:
+        line["c1"] = _c1_bench(tsa, torch, synth, lib, sh)
     if not args.no_minimap:
         line["minimap"] = _minimap_bench(tsa, torch, api, lib, dev, sh, args.region_reps)
     if not args.no_spectrum:
