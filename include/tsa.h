@@ -118,8 +118,9 @@ size_t tsa_workspace_bytes(int32_t op, const tsa_cube* cube, const tsa_region* r
  * Global moments (Section 4.2, with min/max of Section 4.1): count, nan_count,
  * mean, m2, std, min, max of the non-NaN voxels of `region` (host pointer or
  * NULL).  Writes those fields and status/flags of *d_out (device pointer); the
- * median field is left untouched.  Per-lane sums are float-float, block
- * partials are merged in double in a fixed order (deterministic).
+ * median field is left untouched.  Per-lane sums are double (float32 cubes)
+ * or exact integers (int16), block partials are merged in double in a fixed
+ * order (deterministic).
  */
 int tsa_moments(const tsa_cube* cube, const tsa_region* region, tsa_result* d_out, void* d_ws,
                 size_t ws_bytes, tsa_stream_t stream);

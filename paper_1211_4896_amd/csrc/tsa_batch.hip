@@ -50,7 +50,6 @@ struct QState {
   uint32_t skip2, need3, compact, cand_base, cand_n, cand_fill;
   uint32_t prefix, hist_ok, var_on, finished;
   float lo, hi, scale, shift;
-  int32_t vscale, pad;
   uint64_t n, k;
 };
 
@@ -76,7 +75,7 @@ struct BArgs {
   uint64_t* tile_base;
   uint32_t* tile_q;  // ticket (tile of the batch) -> query
   Partial* parts1;
-  float2* parts2;
+  double* parts2;  // per tile: sum of squared deviations about the shift
   uint32_t* digits;
   uint32_t* pool;
 };
@@ -237,7 +236,12 @@ TSA_DEV bool block_wait_ge(const uint32_t* p, uint32_t v, uint32_t* err, BShared
         if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
         if (wall_clock64() - t0 > kWaitTicks) break;
       }
-      __builtin_amdgcn_s_sleep(4);
+      // back off after a few quick polls: hundreds of waiting blocks polling
+      // one word at full rate slow down the loads of the blocks still working
+      if (it < 16)
+        __builtin_amdgcn_s_sleep(4);
+      else
+        __builtin_amdgcn_s_sleep(127);
     }
     if (!ok) atomicOr(err, 1u);
     sh.flag = ok;
@@ -317,7 +321,7 @@ TSA_DEV void epilogue1(const BArgs& a, uint32_t q, BShared& sh, uint32_t* lds) {
           R.flags |= TSA_FLAG_HIST_SKIPPED;  // an infinite range has no bins
         s.finished = 1;
       } else {
-        const double q2 = ep.mq[0] > 0.0 ? ep.mq[0] : 0.0;
+        const double q2 = ep.mq[0] < 0.0 ? 0.0 : ep.mq[0];  // NaN (infinite values) stays
         R.mean = mean;
         R.m2 = q2;
         R.std = sqrt(q2 / (double)cnt);
@@ -354,13 +358,8 @@ TSA_DEV void epilogue1(const BArgs& a, uint32_t q, BShared& sh, uint32_t* lds) {
         s.scale = scale;
         s.hist_ok = ok;
         if (!ok) R.flags |= TSA_FLAG_HIST_SKIPPED;
-        s.var_on = (DT == 0 && isfinite(mean) &&
-                    one_pass_m2_at_risk(mean, R.m2 / (double)cnt, fmax(fabs((double)lo), fabs((double)hi))))
-                       ? 1u
-                       : 0u;
+        s.var_on = (DT == 0 && isfinite(mean) && one_pass_m2_at_risk(mean, R.m2 / (double)cnt)) ? 1u : 0u;
         s.shift = s.var_on ? (float)mean : 0.0f;
-        s.vscale = s.var_on ? var_scale_exp(fmax(fabs((double)hi - (double)s.shift), fabs((double)lo - (double)s.shift)))
-                            : 0;
         s.compact = 0;
         if (bucket <= a.cand_max) {
           const uint32_t base = atomicAdd(&a.hdr->pool_top, (uint32_t)bucket);
@@ -394,7 +393,7 @@ TSA_DEV void epilogue2(const BArgs& a, uint32_t q, BShared& sh, uint32_t* lds) {
     if (DT == 0 && s.var_on) {
       const uint64_t tb = a.tile_base[q];
       double x = 0.0;
-      for (uint32_t i = t; i < g.ntiles; i += bs) x += (double)a.parts2[tb + i].x + (double)a.parts2[tb + i].y;
+      for (uint32_t i = t; i < g.ntiles; i += bs) x += a.parts2[tb + i];
       ep.mm[t] = x;
       __syncthreads();
       for (int s2 = bs / 2; s2 > 0; s2 >>= 1) {
@@ -403,8 +402,8 @@ TSA_DEV void epilogue2(const BArgs& a, uint32_t q, BShared& sh, uint32_t* lds) {
       }
       if (t == 0) {
         const double dm = R.mean - (double)s.shift;
-        double m2 = ldexp(ep.mm[0], -2 * s.vscale) - (double)n * dm * dm;
-        if (!(m2 > 0.0)) m2 = 0.0;
+        double m2 = ep.mm[0] - (double)n * dm * dm;
+        if (m2 < 0.0) m2 = 0.0;  // rounding below zero; NaN (infinite values) stays
         R.m2 = m2;
         R.std = sqrt(m2 / (double)n);
       }
@@ -554,15 +553,12 @@ __global__ __launch_bounds__(kBBlock) void k_batch(BArgs a) {
       if (!block_wait_ge(&a.hdr->p2_done, (uint32_t)a.nq, &a.hdr->err, sh)) return;
       if (__hip_atomic_load(&a.hdr->any3, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0 || lt >= T1) return;
     }
-    // ticket -> (query, tile).  Tiles are visited in the order of the
-    // bijection lt -> lt * (2^31 - 1) mod T1 (the multiplier is prime and
-    // exceeds T1), so blocks running at the same time work on different boxes
-    // instead of all adding into one box's counters.
+    // ticket -> (query, tile).  Tiles are taken box after box, so each box
+    // finishes its phase early and its next-phase tiles seldom wait for it.
     if (t == 0) {
-      const uint64_t pt = (lt * 2147483647ull) % T1;
-      const uint32_t qq = a.tile_q[pt];
+      const uint32_t qq = a.tile_q[lt];
       sh.q = qq;
-      sh.tile = (uint32_t)(pt - a.tile_base[qq]);
+      sh.tile = (uint32_t)(lt - a.tile_base[qq]);
     }
     __syncthreads();
     const uint32_t q = sh.q, tile = sh.tile;
@@ -598,7 +594,7 @@ __global__ __launch_bounds__(kBBlock) void k_batch(BArgs a) {
         BPass2<DT> f{HistOwnAcc{lds, s.lo, s.scale, a.nbins - 1, a.rshift, (uint32_t)t & ((1u << a.rshift) - 1u)},
                      Level2Acc<DT>{l2, s.prefix >> kShift1, s.compact != 0,
                                    cand_sink(cs, a.pool + s.cand_base, &s.cand_fill, s.cand_n)},
-                     VarAcc{s.shift, s.vscale}, hist_on, var_on};
+                     VarAcc{s.shift}, hist_on, var_on};
         walk_tile<DT, VEC, NT>(a, g, tile, f);
         f.l2.finish();
         __syncthreads();
@@ -610,25 +606,14 @@ __global__ __launch_bounds__(kBBlock) void k_batch(BArgs a) {
         }
         if (var_on) {
           __syncthreads();
-          float h, l;
-          two_sum(f.var.qh, f.var.ql, h, l);
-          f.var.qh = h;
-          f.var.ql = l;
-#pragma unroll
-          for (int o = 32; o > 0; o >>= 1) {
-            const float bqh = __shfl_xor(f.var.qh, o), bql = __shfl_xor(f.var.ql, o);
-            dw_add(f.var.qh, f.var.ql, bqh, bql);
-          }
+          const double vq = wave_sum_f64(f.var.q);
           const int w = t / kWave, lane = t % kWave;
-          if (lane == 0) {
-            sh.mom.qh[w] = f.var.qh;
-            sh.mom.ql[w] = f.var.ql;
-          }
+          if (lane == 0) sh.mom.q[w] = vq;
           __syncthreads();
           if (t == 0) {
-            float qh = sh.mom.qh[0], ql = sh.mom.ql[0];
-            for (int i = 1; i < kBBlock / kWave; ++i) dw_add(qh, ql, sh.mom.qh[i], sh.mom.ql[i]);
-            a.parts2[a.tile_base[q] + tile] = make_float2(qh, ql);
+            double bq = sh.mom.q[0];
+            for (int i = 1; i < kBBlock / kWave; ++i) bq += sh.mom.q[i];
+            a.parts2[a.tile_base[q] + tile] = bq;
           }
         }
       }
@@ -708,7 +693,7 @@ static BLayout batch_layout(int32_t nq) {
   L.parts1 = o;
   o = al(o + sizeof(Partial) * (size_t)nq * mt);
   L.parts2 = o;
-  o = al(o + sizeof(float2) * (size_t)nq * mt);
+  o = al(o + sizeof(double) * (size_t)nq * mt);
   L.digits = o;
   o = al(o + 4 * (size_t)kBins1 * nq);
   uint64_t pk = (uint64_t)kPoolPerQuery * (uint64_t)nq;
@@ -886,7 +871,7 @@ static int enqueue_region_batch(const tsa_cube* cube, const tsa_region* d_region
   a.tile_base = (uint64_t*)(ws + L.tile_base);
   a.tile_q = (uint32_t*)(ws + L.tile_q);
   a.parts1 = (Partial*)(ws + L.parts1);
-  a.parts2 = (float2*)(ws + L.parts2);
+  a.parts2 = (double*)(ws + L.parts2);
   a.digits = (uint32_t*)(ws + L.digits);
   a.pool = (uint32_t*)(ws + L.pool);
   const size_t lds1 = ((size_t)kBins1 + kTrash) * 4;

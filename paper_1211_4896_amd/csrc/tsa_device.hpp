@@ -18,18 +18,12 @@ constexpr int kWave = 64;
 constexpr int kShift1 = 20, kShift2 = 8;
 constexpr int kBins1 = 4096, kBins2 = 4096, kBins3 = 256;
 
-// Whether the one-pass M2 = Q - S^2/n (float-float Q and S) can miss the
-// stated accuracy: cancellation when mean^2 > 9 var (the error grows with
-// 1 + mean^2/var), or single-precision squares near overflow or underflow.
-TSA_DEV bool one_pass_m2_at_risk(double mean, double var1, double amax) {
-  return !(var1 > 0.0) || mean * mean > 9.0 * var1 || amax > 0x1p50 || amax < 0x1p-50;
-}
-
-// Exponent s with 2^s * dev near 2^40: squares of scaled deviations stay far
-// from float overflow and underflow for any finite extent dev > 0.
-TSA_DEV int32_t var_scale_exp(double dev) {
-  if (!(dev > 0.0) || !isfinite(dev)) return 0;
-  return 40 - ilogb(dev);
+// Whether the one-pass M2 = Q - S^2/n can miss the stated accuracy: its
+// relative error grows with 1 + mean^2/var (cancellation), so past
+// mean^2 > 9 var the second moment is recomputed about the mean.  Squares of
+// float32 values lie in [2^-298, 2^256] and never leave the double range.
+TSA_DEV bool one_pass_m2_at_risk(double mean, double var1) {
+  return !(var1 > 0.0) || mean * mean > 9.0 * var1;
 }
 
 // ---- order-preserving keys -------------------------------------------------
@@ -99,38 +93,6 @@ TSA_DEV uint4 load16(const uint4* p) {
   return r;
 }
 
-// ---- error-free transformations (float) -----------------------------------
-// TwoSum (Knuth): s + e == a + b exactly.
-TSA_DEV void two_sum(float a, float b, float& s, float& e) {
-  s = a + b;
-  float bp = s - a;
-  e = (a - (s - bp)) + (b - bp);
-}
-// Fast2Sum (Dekker): exact when exponent(a) >= exponent(b) or a == 0.
-TSA_DEV void fast_two_sum(float a, float b, float& s, float& e) {
-  s = a + b;
-  float z = s - a;
-  e = b - z;
-}
-// Sum of two non-negative floats with its exact rounding error: Fast2Sum with
-// the larger operand first (for a, b >= 0 the larger value is the larger
-// magnitude), one operation cheaper than TwoSum and the same (s, e).
-TSA_DEV void two_sum_nonneg(float a, float b, float& s, float& e) {
-  const float big = fmaxf(a, b), small = fminf(a, b);
-  s = a + b;
-  e = small - (s - big);
-}
-// Double-word + double-word (Joldes, Muller & Popescu 2017, "AccurateDWPlusDW").
-TSA_DEV void dw_add(float& ah, float& al, float bh, float bl) {
-  float sh, sl, th, tl, vh, vl;
-  two_sum(ah, bh, sh, sl);
-  two_sum(al, bl, th, tl);
-  float c = sl + th;
-  fast_two_sum(sh, c, vh, vl);
-  float w = tl + vl;
-  fast_two_sum(vh, w, ah, al);
-}
-
 // ---- wave / block reductions -------------------------------------------------
 TSA_DEV uint32_t wave_sum_u32(uint32_t v) {
 #pragma unroll
@@ -159,12 +121,12 @@ TSA_DEV int64_t wave_sum_i64(int64_t v) {
 }
 
 // ---- per-block moment partial ------------------------------------------------
-// float32 cubes: float-float sums (sh+sl = sum x, qh+ql = sum x^2);
+// float32 cubes: double sums s = sum x, q = sum x^2 (or of squared deviations);
 // int16 cubes: exact integer sums si, qi.  Keys give min/max.
 struct Partial {
   uint64_t n;
   uint32_t kmin, kmax;
-  float sh, sl, qh, ql;
+  double s, q;
   int64_t si;
   uint64_t qi;
 };
@@ -186,7 +148,7 @@ struct SelState {
   float lo, hi, scale;
   float shift;        // fused path: fl32(mean) that pass B subtracts before squaring
   uint32_t var_on;    // fused path: pass B recomputes M2 about `shift`
-  int32_t vscale;     // fused path: deviations are scaled by 2^vscale before squaring
+  uint32_t pad0;
   double q;           // rank_mode 1: the rank is floor(q (n - 1))
   uint32_t rank_mode; // 0: lower median, 1: quantile q
   uint32_t levels;    // digits to select before stopping (3 = exact)

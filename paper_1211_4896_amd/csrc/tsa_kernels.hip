@@ -128,10 +128,8 @@ TSA_DEV void partial_stats(const Partial& p, int dtype, double& n, double& m, do
     return;
   }
   if (dtype == 0) {
-    const double S = (double)p.sh + (double)p.sl;
-    const double Q = (double)p.qh + (double)p.ql;
-    m = S / n;
-    q = Q - S * m;
+    m = p.s / n;
+    q = p.q - p.s * m;
   } else {
     // exact n*Q - S^2 in 128-bit integers, then one rounding to double
     const __int128 num = (__int128)p.qi * (__int128)p.n - (__int128)p.si * (__int128)p.si;
@@ -204,7 +202,7 @@ TSA_DEV void merge_moments(const Partial* __restrict__ parts, int np, int dtype,
         out->m2 = 0.0;
         out->std = 0.0;
       } else {
-        const double m2 = sm.q[0] > 0.0 ? sm.q[0] : 0.0;
+        const double m2 = sm.q[0] < 0.0 ? 0.0 : sm.q[0];  // NaN (infinite values) stays
         out->mean = sm.m[0];
         out->m2 = m2;
         out->std = sqrt(m2 / N);
@@ -504,13 +502,10 @@ __global__ __launch_bounds__(1024) void k_mid(const Partial* __restrict__ parts,
     st->scale = scale;
     // pass B recomputes M2 about c = fl32(mean) when the values differ (float32 cubes)
     const double mean = out->mean;
-    const double amax = fmax(fabs((double)lo), fabs((double)hi));
     const bool von = dtype == 0 && n > 0 && kmin != kmax && isfinite(mean) &&
-                     one_pass_m2_at_risk(mean, out->m2 / (double)n, amax);
+                     one_pass_m2_at_risk(mean, out->m2 / (double)n);
     st->shift = von ? (float)mean : 0.0f;
     st->var_on = von ? 1u : 0u;
-    st->vscale = von ? var_scale_exp(fmax(fabs((double)hi - (double)(float)mean), fabs((double)lo - (double)(float)mean)))
-                     : 0;
     out->flags = ok ? 0 : TSA_FLAG_HIST_SKIPPED;
     out->median = __builtin_nan("");
   }
@@ -571,7 +566,7 @@ __global__ __launch_bounds__(1024) void k_pass_b(Geom g, int32_t nbins, uint32_t
   __syncthreads();
   PassB<DT> b{HistOwnAcc{lds, st->lo, st->scale, nbins - 1, rshift, threadIdx.x & ((1u << rshift) - 1u)},
               Level2Acc<DT>{l2, sel_on ? (st->prefix >> kShift1) : 0xFFFFFFFFu, sel_on && st->compact != 0, sink},
-              VarAcc{st->shift, st->vscale}, hist_on, var_on};
+              VarAcc{st->shift}, hist_on, var_on};
   walk<DT, VEC, kUnroll, NT>(g, b);
   b.l2.finish();
   __syncthreads();
@@ -620,7 +615,7 @@ __global__ __launch_bounds__(1024) void k_pass_bwin(Geom g, int32_t nbins, SelSt
   const int32_t w0 = st->win0;
   PassBWin<DT> b{HistWinAcc{lds, st->lo, st->scale, nbins - 1, w0, counts},
                  Level2Acc<DT>{l2, sel_on ? (st->prefix >> kShift1) : 0xFFFFFFFFu, sel_on && st->compact != 0, sink},
-                 VarAcc{st->shift, st->vscale}, hist_on, var_on};
+                 VarAcc{st->shift}, hist_on, var_on};
   walk<DT, VEC, kUnroll, NT>(g, b);
   b.l2.finish();
   __syncthreads();
@@ -677,7 +672,7 @@ __global__ __launch_bounds__(1024) void k_pass_b16(Geom g, int32_t nbins, uint32
   PassB16<DT> b{Hist16Acc{lds, st->lo, st->hi, st->scale, nbins - 1, 0, nbins, counts, epoch, 0u, true, 0u, 0u},
                 Level2Acc<DT>{l2, sel_on ? (st->prefix >> kShift1) : 0xFFFFFFFFu, sel_on && st->compact != 0,
                               cand_sink(cs, cand, &st->ncand, st->cand_cap)},
-                VarAcc{st->shift, st->vscale}, hist_on, var_on};
+                VarAcc{st->shift}, hist_on, var_on};
   walk<DT, VEC, kUnroll, NT>(g, b);
   b.l2.finish();
   if (hist_on) b.h.flush();
@@ -695,7 +690,7 @@ __global__ __launch_bounds__(1024) void k_var_finish(const Partial* __restrict__
   if (!st->var_on) return;
   const int t = threadIdx.x, bs = blockDim.x;
   double q = 0.0;
-  for (int i = t; i < np; i += bs) q += (double)parts2[i].qh + (double)parts2[i].ql;
+  for (int i = t; i < np; i += bs) q += parts2[i].q;
   sq[t] = q;
   __syncthreads();
   for (int s2 = bs / 2; s2 > 0; s2 >>= 1) {
@@ -705,8 +700,8 @@ __global__ __launch_bounds__(1024) void k_var_finish(const Partial* __restrict__
   if (t == 0) {
     const double n = (double)out->count;
     const double dm = out->mean - (double)st->shift;
-    double m2 = ldexp(sq[0], -2 * st->vscale) - n * dm * dm;
-    if (!(m2 > 0.0)) m2 = 0.0;
+    double m2 = sq[0] - n * dm * dm;
+    if (m2 < 0.0) m2 = 0.0;  // rounding below zero; NaN (infinite values) stays
     out->m2 = m2;
     out->std = sqrt(m2 / n);
   }

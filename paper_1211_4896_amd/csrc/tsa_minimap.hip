@@ -271,17 +271,17 @@ struct MMShared {
   uint32_t kmin, kmax, prefix, go;
   float lo, hi, scale, shift;
   uint32_t hist_ok, var_on;
-  int32_t vscale;
   uint32_t status;
 };
 
 // One workgroup per cell, the cell held in registers: lane t keeps voxels
 // t + 1024 j (j < EPT) of the cell, so a 30^3 cell is 27 values per lane, all
-// loaded at once, and the LDS holds only counters.  The float-float moments
-// over the cell's values bound this kernel by VALU issue, not by HBM.
-// Every value is held as float32: int16 converts exactly, its float-float sums
-// stay exact (partial sums below 2^48) and float keys order it the same way,
-// and slots past the cell hold NaN, so no per-slot validity test is needed.  Block b works on cell (b % 8) * per_xcd + b / 8,
+// loaded at once, and the LDS holds only counters.  The per-value work
+// (moments, keys, digits, histogram) bounds this kernel by VALU issue, not
+// by HBM.  Every value is held as float32: int16 converts exactly, its double
+// sums stay exact (a cell's sums of squares stay below 2^53) and float keys
+// order it the same way, and slots past the cell hold NaN, so no per-slot
+// validity test is needed.  Block b works on cell (b % 8) * per_xcd + b / 8,
 // so the cells one XCD (and its L2) sees are neighbours sharing cache lines at
 // their x edges.
 template <int DT, int EPT>
@@ -389,7 +389,7 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
         sh.hist_ok = isfinite(lo) ? 2u : 0u;  // 2: every value in bin 0
         if (!sh.hist_ok) R.flags = TSA_FLAG_HIST_SKIPPED;
       } else {
-        if (!(m2 > 0.0)) m2 = 0.0;
+        if (m2 < 0.0) m2 = 0.0;  // rounding below zero; NaN (infinite values) stays
         R.mean = mean;
         R.m2 = m2;
         R.std = sqrt(m2 / n);
@@ -406,11 +406,8 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
         if (!sh.hist_ok) R.flags = TSA_FLAG_HIST_SKIPPED;
         sh.lo = lo;
         sh.scale = scale;
-        sh.var_on = (isfinite(mean) && one_pass_m2_at_risk(mean, m2 / n, fmax(fabs(vmin), fabs(vmax))))
-                        ? 1u
-                        : 0u;
+        sh.var_on = (isfinite(mean) && one_pass_m2_at_risk(mean, m2 / n)) ? 1u : 0u;
         sh.shift = sh.var_on ? (float)mean : 0.0f;
-        sh.vscale = sh.var_on ? var_scale_exp(fmax(fabs(vmax - (double)sh.shift), fabs(vmin - (double)sh.shift))) : 0;
       }
     }
   }
@@ -424,7 +421,7 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
     for (uint32_t i = t; i < kBins2; i += kMMBlock) dig[i] = 0u;
     __syncthreads();
     HistOwnAcc hacc{hist, sh.lo, sh.scale, a.nbins - 1, a.rshift, (uint32_t)t & ((1u << a.rshift) - 1u)};
-    VarAcc var{sh.shift, sh.vscale};
+    VarAcc var{sh.shift};
     const bool hist_on = sh.hist_ok != 0, var_on = sh.var_on != 0;
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
@@ -438,8 +435,8 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
     if (t == 0 && var_on) {
       const double n = (double)sh.cnt;
       const double dm = R.mean - (double)sh.shift;
-      double m2 = ldexp((double)sh.part.qh + (double)sh.part.ql, -2 * sh.vscale) - n * dm * dm;
-      if (!(m2 > 0.0)) m2 = 0.0;
+      double m2 = sh.part.q - n * dm * dm;
+      if (m2 < 0.0) m2 = 0.0;  // rounding below zero; NaN (infinite values) stays
       R.m2 = m2;
       R.std = sqrt(m2 / n);
     }

@@ -39,23 +39,20 @@ struct Elt<1> {
 template <int DT, bool COUNT = true>
 struct MomAcc;
 
+// float32: per-lane running sums in double.  Each value and its square are
+// exact in double (a float32 square needs 48 significand bits and lies in
+// [2^-298, 2^256]), so every step rounds once, with relative error 2^-53.
+// gfx950 issues double adds and fused multiply-adds at the single-precision
+// rate, which makes this both cheaper and more accurate than float-float sums.
 template <bool COUNT>
 struct MomAcc<0, COUNT> {
-  float sh = 0.f, sl = 0.f, qh = 0.f, ql = 0.f;
+  double s = 0.0, q = 0.0;
   uint32_t kmin = 0xFFFFFFFFu, kmax = 0u, cnt = 0u;
   TSA_DEV void operator()(float x, bool in) {
     const bool ok = Elt<0>::valid(x, in);
-    const float v = ok ? x : 0.0f;
-    float s, e;
-    two_sum(sh, v, s, e);
-    sh = s;
-    sl += e;
-    const float p = v * v;
-    const float pe = __builtin_fmaf(v, v, -p);
-    float q, eq;
-    two_sum_nonneg(qh, p, q, eq);  // qh, p >= 0
-    qh = q;
-    ql += eq + pe;
+    const double v = (double)(ok ? x : 0.0f);
+    s += v;
+    q = __builtin_fma(v, v, q);
     const uint32_t k = Elt<0>::key(x);
     kmin = min(kmin, ok ? k : 0xFFFFFFFFu);
     kmax = max(kmax, ok ? k : 0u);
@@ -90,29 +87,22 @@ struct MomAcc<1, COUNT> {
 
 // Reduce a block's lanes (fixed order) and store one Partial.
 struct alignas(16) MomShared {
-  float sh[16], sl[16], qh[16], ql[16];
+  double s[16], q[16];
   int64_t si[16];
   uint64_t qi[16];
   uint32_t kmin[16], kmax[16];
   uint64_t cnt[16];
 };
 
+TSA_DEV double wave_sum_f64(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);  // a + b == b + a: every lane ends equal
+  return v;
+}
+
 template <bool COUNT>
 TSA_DEV void block_store_partial(MomAcc<0, COUNT>& a, MomShared& sm, Partial* out) {
-  float h, l;
-  two_sum(a.sh, a.sl, h, l);
-  a.sh = h;
-  a.sl = l;
-  two_sum(a.qh, a.ql, h, l);
-  a.qh = h;
-  a.ql = l;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const float bsh = __shfl_xor(a.sh, o), bsl = __shfl_xor(a.sl, o);
-    const float bqh = __shfl_xor(a.qh, o), bql = __shfl_xor(a.ql, o);
-    dw_add(a.sh, a.sl, bsh, bsl);
-    dw_add(a.qh, a.ql, bqh, bql);
-  }
+  const double s = wave_sum_f64(a.s), q = wave_sum_f64(a.q);
   const uint32_t kmin = wave_min_u32(a.kmin), kmax = wave_max_u32(a.kmax);
 #if TSA_BALLOT_COUNT
   const uint64_t cnt = a.cnt;  // already the wave's total
@@ -121,10 +111,8 @@ TSA_DEV void block_store_partial(MomAcc<0, COUNT>& a, MomShared& sm, Partial* ou
 #endif
   const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   if (lane == 0) {
-    sm.sh[w] = a.sh;
-    sm.sl[w] = a.sl;
-    sm.qh[w] = a.qh;
-    sm.ql[w] = a.ql;
+    sm.s[w] = s;
+    sm.q[w] = q;
     sm.kmin[w] = kmin;
     sm.kmax[w] = kmax;
     sm.cnt[w] = cnt;
@@ -132,12 +120,12 @@ TSA_DEV void block_store_partial(MomAcc<0, COUNT>& a, MomShared& sm, Partial* ou
   __syncthreads();
   if (threadIdx.x == 0) {
     const int nw = blockDim.x / kWave;
-    float sh = sm.sh[0], sl = sm.sl[0], qh = sm.qh[0], ql = sm.ql[0];
+    double bs = sm.s[0], bq = sm.q[0];
     uint32_t mn = sm.kmin[0], mx = sm.kmax[0];
     uint64_t n = sm.cnt[0];
     for (int i = 1; i < nw; ++i) {
-      dw_add(sh, sl, sm.sh[i], sm.sl[i]);
-      dw_add(qh, ql, sm.qh[i], sm.ql[i]);
+      bs += sm.s[i];
+      bq += sm.q[i];
       mn = min(mn, sm.kmin[i]);
       mx = max(mx, sm.kmax[i]);
       n += sm.cnt[i];
@@ -146,10 +134,8 @@ TSA_DEV void block_store_partial(MomAcc<0, COUNT>& a, MomShared& sm, Partial* ou
     p.n = n;
     p.kmin = mn;
     p.kmax = mx;
-    p.sh = sh;
-    p.sl = sl;
-    p.qh = qh;
-    p.ql = ql;
+    p.s = bs;
+    p.q = bq;
     p.si = 0;
     p.qi = 0;
     *out = p;
@@ -186,62 +172,41 @@ TSA_DEV void block_store_partial(MomAcc<1, COUNT>& a, MomShared& sm, Partial* ou
       p.kmax = max(p.kmax, sm.kmax[i]);
       p.n += sm.cnt[i];
     }
-    p.sh = p.sl = p.qh = p.ql = 0.f;
+    p.s = p.q = 0.0;
     *out = p;
   }
 }
 
 // ---- second moment about a shift (two-pass form, fused path) ----------------
-// sum (x - c)^2 with x - c split exactly into d + e by TwoSum, so the squares
-// carry no cancellation however large the mean is against the spread; d and e
-// are scaled by a power of two chosen from the data's extent, so the squares
-// stay inside the float range for denormal and for huge values alike.
+// sum (x - c)^2 in double: the difference of two float32 values is formed in
+// double (exact unless their exponents lie more than 29 apart, then within
+// 2^-53), so the squares carry no cancellation however large the mean is
+// against the spread, and they stay inside [2^-298, 2^258].
 struct VarAcc {
   float c;
-  int32_t sc;  // deviations are scaled by 2^sc (exact) so their squares neither overflow nor underflow
-  float qh = 0.f, ql = 0.f;
+  double q = 0.0;
   TSA_DEV void operator()(float x, bool in) {
     const bool ok = in && (x == x);
-    float d, e;
-    two_sum(ok ? x : c, -c, d, e);  // masked lanes: d = e = 0
-    d = __builtin_amdgcn_ldexpf(d, sc);
-    e = __builtin_amdgcn_ldexpf(e, sc);
-    const float p = d * d;
-    const float pe = __builtin_fmaf(d, d, -p);
-    float q, eq;
-    two_sum_nonneg(qh, p, q, eq);  // qh, p >= 0
-    qh = q;
-    ql += eq + __builtin_fmaf(2.0f * d, e, pe);
+    const double d = (double)(ok ? x : c) - (double)c;  // masked lanes: d = 0
+    q = __builtin_fma(d, d, q);
   }
   TSA_DEV void chunk() {}
 };
 
 TSA_DEV void block_store_var(VarAcc& a, MomShared& sm, Partial* out) {
-  float h, l;
-  two_sum(a.qh, a.ql, h, l);
-  a.qh = h;
-  a.ql = l;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const float bqh = __shfl_xor(a.qh, o), bql = __shfl_xor(a.ql, o);
-    dw_add(a.qh, a.ql, bqh, bql);
-  }
+  const double q = wave_sum_f64(a.q);
   const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  if (lane == 0) {
-    sm.qh[w] = a.qh;
-    sm.ql[w] = a.ql;
-  }
+  if (lane == 0) sm.q[w] = q;
   __syncthreads();
   if (threadIdx.x == 0) {
     const int nw = blockDim.x / kWave;
-    float qh = sm.qh[0], ql = sm.ql[0];
-    for (int i = 1; i < nw; ++i) dw_add(qh, ql, sm.qh[i], sm.ql[i]);
+    double bq = sm.q[0];
+    for (int i = 1; i < nw; ++i) bq += sm.q[i];
     Partial p;
     p.n = 0;
     p.kmin = p.kmax = 0;
-    p.sh = p.sl = 0.f;
-    p.qh = qh;
-    p.ql = ql;
+    p.s = 0.0;
+    p.q = bq;
     p.si = 0;
     p.qi = 0;
     *out = p;
@@ -532,10 +497,8 @@ TSA_DEV void partial_stats_b(const Partial& p, int dtype, double& n, double& m, 
     return;
   }
   if (dtype == 0) {
-    const double S = (double)p.sh + (double)p.sl;
-    const double Q = (double)p.qh + (double)p.ql;
-    m = S / n;
-    q = Q - S * m;
+    m = p.s / n;
+    q = p.q - p.s * m;
   } else {
     const __int128 num = (__int128)p.qi * (__int128)p.n - (__int128)p.si * (__int128)p.si;
     const int64_t hi = (int64_t)(num >> 64);

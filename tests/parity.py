@@ -4,8 +4,10 @@ Tolerances:
 * counts, nan_count, histogram bins, outliers, min, max, median: bit-exact;
 * mean: |gpu - oracle| <= 1e-12 |oracle| + 1e-14 rms(x)   (rms = hypot(mean, std));
   the second term only matters when the mean is ~0 relative to the spread,
-  where a relative bound on the mean is meaningless.  Float-float sums carry
-  ~2^-44 relative error of sum |x|, i.e. well below 1e-14 rms;
+  where a relative bound on the mean is meaningless.  The kernels sum each
+  lane's values in double (one 2^-53 rounding per addition) and merge lanes
+  and blocks in double, so for data of either sign the rounding errors
+  cancel to far below 1e-14 rms;
 * std and m2: relative 1e-12 (exactly 0 when the oracle's is 0).
 """
 import math
