@@ -588,7 +588,6 @@ __global__ __launch_bounds__(kBBlock) void k_batch(BArgs a) {
         const uint32_t hsize = ((uint32_t)a.nbins << a.rshift) + kTrash;
         uint32_t* l2 = lds + hsize;
         lds_zero(lds, hsize + kBins2);
-        cand_init(cs);
         __syncthreads();
         const bool hist_on = s.hist_ok != 0, var_on = DT == 0 && s.var_on != 0;
         BPass2<DT> f{HistOwnAcc{lds, s.lo, s.scale, a.nbins - 1, a.rshift, (uint32_t)t & ((1u << a.rshift) - 1u)},

@@ -64,7 +64,6 @@ __global__ __launch_bounds__(1024) void k_level2(Geom g, SelState* __restrict__ 
   __shared__ CandShared cs;
   if (st->done) return;
   lds_zero(lds, kBins2);
-  cand_init(cs);
   __syncthreads();
   Level2Acc<DT> a{lds, st->prefix >> kShift1, st->compact != 0, cand_sink(cs, cand, &st->ncand, st->cand_cap)};
   walk<DT, VEC, kUnroll, NT>(g, a);
@@ -381,7 +380,6 @@ __global__ __launch_bounds__(1024) void k_mlevel2(Geom g, const SelState* __rest
   __shared__ CandShared cs;
   if (st->done) return;
   lds_zero(lds, kBins2);
-  cand_init(cs);
   __syncthreads();
   float mf;
   int32_t mi;
@@ -562,7 +560,7 @@ __global__ __launch_bounds__(1024) void k_pass_b(Geom g, int32_t nbins, uint32_t
   const bool var_on = DT == 0 && st->var_on != 0;
   if (!hist_on && !sel_on && !var_on) return;
   lds_zero(lds, hsize + kBins2);
-  const CandSink sink = cand_sink_lds(l2 + kBins2, blockDim.x / kWave, cand, &st->ncand, st->cand_cap);
+  const CandSink sink = cand_sink_lds(l2 + kBins2, cand, &st->ncand, st->cand_cap);
   __syncthreads();
   PassB<DT> b{HistOwnAcc{lds, st->lo, st->scale, nbins - 1, rshift, threadIdx.x & ((1u << rshift) - 1u)},
               Level2Acc<DT>{l2, sel_on ? (st->prefix >> kShift1) : 0xFFFFFFFFu, sel_on && st->compact != 0, sink},
@@ -610,7 +608,7 @@ __global__ __launch_bounds__(1024) void k_pass_bwin(Geom g, int32_t nbins, SelSt
   const bool var_on = DT == 0 && st->var_on != 0;
   if (!hist_on && !sel_on && !var_on) return;
   lds_zero(lds, kWinBins + kBins2);
-  const CandSink sink = cand_sink_lds(l2 + kBins2, blockDim.x / kWave, cand, &st->ncand, st->cand_cap);
+  const CandSink sink = cand_sink_lds(l2 + kBins2, cand, &st->ncand, st->cand_cap);
   __syncthreads();
   const int32_t w0 = st->win0;
   PassBWin<DT> b{HistWinAcc{lds, st->lo, st->scale, nbins - 1, w0, counts},
@@ -667,7 +665,6 @@ __global__ __launch_bounds__(1024) void k_pass_b16(Geom g, int32_t nbins, uint32
   const bool var_on = DT == 0 && st->var_on != 0;
   if (!hist_on && !sel_on && !var_on) return;
   lds_zero(lds, hwords + kBins2);
-  cand_init(cs);
   __syncthreads();
   PassB16<DT> b{Hist16Acc{lds, st->lo, st->hi, st->scale, nbins - 1, 0, nbins, counts, epoch, 0u, true, 0u, 0u},
                 Level2Acc<DT>{l2, sel_on ? (st->prefix >> kShift1) : 0xFFFFFFFFu, sel_on && st->compact != 0,
@@ -1119,7 +1116,7 @@ int run_stats(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa
   int st = prepare(cube, region, d_ws, ws_bytes, stream, &P, kBpcStats);
   if (st) return st;
   const size_t budget = P.dev.lds_per_block < 65536 ? P.dev.lds_per_block : 65536;
-  const size_t cand_b = (size_t)(P.block / kWave) * (kWaveStage + 1) * 4;  // pass B's candidate staging
+  const size_t cand_b = (size_t)(P.block / kWave) * kWaveStage * 4;  // pass B's candidate staging
   const bool wide = ((size_t)nbins + kTrash + kBins2) * 4 + cand_b > budget;
   // 16-bit counters: (nbins+1)/2 words + level-2 digits, plus ~10 KB of static LDS
   const size_t lds16 = ((((size_t)nbins + 1) / 2) + kBins2) * 4;
@@ -1164,7 +1161,7 @@ int run_stats(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa
     int grid = P.dev.cus;
     if (grid > P.grid) grid = P.grid;
     np2 = grid;
-    const size_t lds_win = ((size_t)kWinBins + kBins2 + (blk / kWave) * (kWaveStage + 1)) * 4;
+    const size_t lds_win = ((size_t)kWinBins + kBins2 + (blk / kWave) * kWaveStage) * 4;
     if (lds_win + sizeof(MomShared) + 1024 <= P.dev.lds_per_block) {
       int stw = TSA_OK;
       TSA_DISPATCH(cube->dtype, P.vec, tuning().nt,

@@ -529,11 +529,11 @@ struct Digit1Acc {  // top 12 key bits of every valid element
 
 // Candidate keys are staged per wave in LDS and copied to the global list in
 // runs of up to kWaveStage keys, so the global counter sees one atomic per run
-// instead of one per wave instruction.  Each wave owns its stage and its fill
-// word: no block barrier is needed, so the block's waves keep their loads in
-// flight.  Appends may come from divergent code; the fill word lives in LDS so
-// every lane sees the wave's latest fill, and flushes stride over whichever
-// lanes are active.
+// instead of one per wave instruction.  Each wave owns its stage: no block
+// barrier is needed, so the block's waves keep their loads in flight.  The
+// walkers call every accumulator from all lanes at the same points, so the
+// wave's fill count is an ordinary variable that every lane updates alike
+// (kept in a register, no LDS round trip per append).
 constexpr uint32_t kWaveStage = 128;  // staged keys per wave
 constexpr int kMaxWaves = 16;
 
@@ -541,88 +541,64 @@ constexpr int kMaxWaves = 16;
 template <int NW>
 struct CandSharedN {
   uint32_t buf[NW][kWaveStage];
-  // written by one lane, read by all: volatile, so no lane reuses a stale load
-  volatile uint32_t fill[NW];
 };
 using CandShared = CandSharedN<kMaxWaves>;
 
 struct CandSink {
-  uint32_t* buf;          // kWaveStage staged keys per wave
-  volatile uint32_t* fill;  // one fill word per wave
+  uint32_t* buf;      // kWaveStage staged keys per wave
   uint32_t* list;     // global list
   uint32_t* counter;  // global fill counter
   uint32_t cap;       // global capacity
+  uint32_t fill;      // keys this wave has staged (equal in every lane)
 };
 
 template <int NW>
 TSA_DEV CandSink cand_sink(CandSharedN<NW>& cs, uint32_t* list, uint32_t* counter, uint32_t cap) {
-  return CandSink{&cs.buf[0][0], cs.fill, list, counter, cap};
+  return CandSink{&cs.buf[0][0], list, counter, cap, 0u};
 }
 
-// Each wave clears its own fill word (before its first append).
-template <int NW>
-TSA_DEV void cand_init(CandSharedN<NW>& cs) {
-  if (threadIdx.x % kWave == 0) cs.fill[threadIdx.x / kWave] = 0u;
-  __builtin_amdgcn_wave_barrier();
+// Staging carved from dynamic LDS: kWaveStage words per wave of the block.
+TSA_DEV uint32_t cand_lds_words(uint32_t waves) { return waves * kWaveStage; }
+TSA_DEV CandSink cand_sink_lds(uint32_t* base, uint32_t* list, uint32_t* counter, uint32_t cap) {
+  return CandSink{base, list, counter, cap, 0u};
 }
 
-// Staging carved from dynamic LDS: kWaveStage words per wave of the block,
-// then one fill word per wave (cand_lds_words() in all).
-TSA_DEV uint32_t cand_lds_words(uint32_t waves) { return waves * (kWaveStage + 1u); }
-TSA_DEV CandSink cand_sink_lds(uint32_t* base, uint32_t waves, uint32_t* list, uint32_t* counter, uint32_t cap) {
-  volatile uint32_t* fill = base + waves * kWaveStage;
-  if (threadIdx.x % kWave == 0) fill[threadIdx.x / kWave] = 0u;
-  __builtin_amdgcn_wave_barrier();
-  return CandSink{base, fill, list, counter, cap};
-}
-
-// Active lanes of a wave copy its `fill` staged keys out (one global atomic).
+// The wave copies its `fill` staged keys out (one global atomic).  Whole wave.
 TSA_DEV void cand_copy_out(const CandSink& k, uint32_t fill) {
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-  const uint64_t act = __ballot(true);
-  const int leader = __ffsll((unsigned long long)act) - 1;
-  const uint32_t na = (uint32_t)__popcll(act);
-  const uint32_t rank = (uint32_t)__popcll(act & ((1ull << lane) - 1ull));
+  __builtin_amdgcn_wave_barrier();  // the staged writes of every lane come first
   uint32_t g = 0;
-  if (lane == leader) g = atomicAdd(k.counter, fill);
-  g = __shfl(g, leader);
-  for (uint32_t i = rank; i < fill; i += na)
+  if (lane == 0) g = atomicAdd(k.counter, fill);
+  g = __shfl(g, 0);
+  for (uint32_t i = lane; i < fill; i += kWave)
     if (g + i < k.cap) k.list[g + i] = k.buf[w * kWaveStage + i];
-  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_wave_barrier();  // and the reads finish before the stage is refilled
 }
 
 // Wave-aggregated append of the lanes whose flag is set (bal = their ballot).
 // Kept inline: an out-of-line call costs the element loops more than its
 // code size saves (measured on the fused pass B).
-TSA_DEV void cand_append_slow(bool m, uint32_t key, uint64_t bal, const CandSink& k) {
+TSA_DEV void cand_append_slow(bool m, uint32_t key, uint64_t bal, CandSink& k) {
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const uint32_t n = (uint32_t)__popcll(bal);
-  uint32_t fill = k.fill[w];
-  if (fill + n > kWaveStage) {
-    cand_copy_out(k, fill);
-    fill = 0;
+  if (k.fill + n > kWaveStage) {
+    cand_copy_out(k, k.fill);
+    k.fill = 0;
   }
   const uint32_t off = (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
-  if (m) k.buf[w * kWaveStage + fill + off] = key;
-  const uint64_t act = __ballot(true);
-  __builtin_amdgcn_wave_barrier();
-  if (lane == __ffsll((unsigned long long)act) - 1) k.fill[w] = fill + n;
-  __builtin_amdgcn_wave_barrier();
+  if (m) k.buf[w * kWaveStage + k.fill + off] = key;
+  k.fill += n;
 }
 
-TSA_DEV void cand_append(bool m, uint32_t key, const CandSink& k) {
+TSA_DEV void cand_append(bool m, uint32_t key, CandSink& k) {
   const uint64_t bal = __ballot(m);
   if (bal != 0) cand_append_slow(m, key, bal, k);
 }
 
-// Whole wave (all lanes active): copy out what is still staged.
-TSA_DEV void cand_finish(const CandSink& k) {
-  const int w = threadIdx.x / kWave;
-  const uint32_t fill = k.fill[w];
-  if (fill) cand_copy_out(k, fill);
-  __builtin_amdgcn_wave_barrier();
-  if (threadIdx.x % kWave == 0) k.fill[w] = 0u;
-  __builtin_amdgcn_wave_barrier();
+// Whole wave: copy out what is still staged.
+TSA_DEV void cand_finish(CandSink& k) {
+  if (k.fill) cand_copy_out(k, k.fill);
+  k.fill = 0;
 }
 
 template <int DT>

@@ -43,6 +43,21 @@ struct RowCursor {
   int64_t off;         // its index from the box origin, in units
 };
 
+// The elements of one 16-byte vector of a row: in_box masks the lanes before
+// the box's first and past its last element when the vector is the first or
+// last of its row (column j of vpr), and every element when ok is false.
+template <int DT, class F>
+TSA_DEV void visit_row_vec(const uint4& r, uint32_t j, uint32_t vpr, uint32_t head_skip, uint32_t last_valid,
+                           bool ok, F& f) {
+  using TT = Ty<DT>;
+  const bool first = j == 0, last = j == vpr - 1;
+#pragma unroll
+  for (int e = 0; e < TT::EPV; ++e) {
+    const bool in = ok && (!first || (uint32_t)e >= head_skip) && (!last || (uint32_t)e < last_valid);
+    f(TT::get(r, e), in);
+  }
+}
+
 template <int DT, bool VEC, int U, bool NT, class F>
 TSA_DEV void walk_rows(const void* base, int64_t v_origin, int64_t v_ystride, int64_t v_zstride, uint32_t ly,
                        const Magic& ly_m, uint32_t vpr, const Magic& vpr_m, uint32_t head_skip, uint32_t last_valid,
@@ -68,29 +83,23 @@ TSA_DEV void walk_rows(const void* base, int64_t v_origin, int64_t v_ystride, in
     c[u].ry = row - c[u].rz * ly;
     c[u].off = (int64_t)c[u].rz * v_zstride + (int64_t)c[u].ry * v_ystride + c[u].j;
   }
-  for (uint32_t li0 = 0; li0 < cnt; li0 += step) {
+  const uint4* vb = (const uint4*)base + v_origin;
+  const T* sb = (const T*)base + v_origin;
+  // full steps: every unit of the step lies in the tile, no per-unit test
+  uint32_t li0 = 0;
+  for (; li0 + step <= cnt; li0 += step) {
     if constexpr (VEC) {
-      const uint4* vb = (const uint4*)base + v_origin;
       uint4 r[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (li0 + u * bs + threadIdx.x < cnt) r[u] = load16<NT>(vb + c[u].off);
+      for (int u = 0; u < U; ++u) r[u] = load16<NT>(vb + c[u].off);
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (li0 + u * bs + threadIdx.x < cnt) {
-          const bool first = c[u].j == 0, last = c[u].j == vpr - 1;
-#pragma unroll
-          for (int e = 0; e < TT::EPV; ++e) {
-            const bool in = (!first || (uint32_t)e >= head_skip) && (!last || (uint32_t)e < last_valid);
-            f(TT::get(r[u], e), in);
-          }
-        }
-      }
+      for (int u = 0; u < U; ++u) visit_row_vec<DT>(r[u], c[u].j, vpr, head_skip, last_valid, true, f);
     } else {
-      const T* sb = (const T*)base + v_origin;
+      T v[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (li0 + u * bs + threadIdx.x < cnt) f(sb[c[u].off], true);
+      for (int u = 0; u < U; ++u) v[u] = sb[c[u].off];
+#pragma unroll
+      for (int u = 0; u < U; ++u) f(v[u], true);
     }
     // advance every cursor by step units
 #pragma unroll
@@ -113,13 +122,40 @@ TSA_DEV void walk_rows(const void* base, int64_t v_origin, int64_t v_ystride, in
     }
     f.chunk();
   }
+  // the last, partial step: units past the tile load nothing and reach f
+  // with in_box false, so every lane still calls f at the same points
+  if (li0 < cnt) {
+    if constexpr (VEC) {
+      uint4 r[U];
+      bool ok[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        ok[u] = li0 + u * bs + threadIdx.x < cnt;
+        r[u] = make_uint4(0u, 0u, 0u, 0u);
+        if (ok[u]) r[u] = load16<NT>(vb + c[u].off);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) visit_row_vec<DT>(r[u], c[u].j, vpr, head_skip, last_valid, ok[u], f);
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool ok = li0 + u * bs + threadIdx.x < cnt;
+        T v = (T)0;
+        if (ok) v = sb[c[u].off];
+        f(v, ok);
+      }
+    }
+    f.chunk();
+  }
 }
 
-// f(T value, bool in_box) is called once per element; in_box is false only
-// for the masked lanes of the first/last vector of a row.  f.chunk() is
-// called by every thread of the block at the same points, after at most
-// blockDim.x * U vectors have been visited since the previous call, so it may
-// synchronise the block.
+// f(T value, bool in_box) is called once per element slot; in_box is false
+// for the masked lanes of the first/last vector of a row and for slots past
+// the end of the work.  Every lane of the block calls f at the same points
+// (never from divergent code), so f may use wave-wide operations that need
+// every lane.  f.chunk() is called by every thread of the block at the same
+// points, after at most blockDim.x * U vectors have been visited since the
+// previous call, so it may synchronise the block.
 template <int DT, bool VEC, int U, bool NT, class F>
 TSA_DEV void walk(const Geom& g, F& f) {
   using TT = Ty<DT>;
@@ -142,22 +178,34 @@ TSA_DEV void walk(const Geom& g, F& f) {
 #pragma unroll
             for (int e = 0; e < TT::EPV; ++e) f(TT::get(r[u], e), true);
           }
-        } else {  // the last, partial chunk of a block
+        } else {  // the last, partial chunk of a block: lanes past the end see in_box false
 #pragma unroll
           for (int u = 0; u < U; ++u) {
             const int64_t j = i + u * bs;
-            if (j < g.v1) {
-              uint4 r = load16<NT>(vb + j);
+            const bool ok = j < g.v1;
+            uint4 r = make_uint4(0u, 0u, 0u, 0u);
+            if (ok) r = load16<NT>(vb + j);
 #pragma unroll
-              for (int e = 0; e < TT::EPV; ++e) f(TT::get(r, e), true);
-            }
+            for (int e = 0; e < TT::EPV; ++e) f(TT::get(r, e), ok);
           }
         }
         f.chunk();
       }
       if (blockIdx.x == 0) {
-        for (int64_t e = g.h0 + threadIdx.x; e < g.h1; e += bs) f(sb[e], true);
-        for (int64_t e = g.t0 + threadIdx.x; e < g.t1; e += bs) f(sb[e], true);
+        for (int64_t e0 = g.h0; e0 < g.h1; e0 += bs) {
+          const int64_t e = e0 + threadIdx.x;
+          const bool ok = e < g.h1;
+          T v = (T)0;
+          if (ok) v = sb[e];
+          f(v, ok);
+        }
+        for (int64_t e0 = g.t0; e0 < g.t1; e0 += bs) {
+          const int64_t e = e0 + threadIdx.x;
+          const bool ok = e < g.t1;
+          T v = (T)0;
+          if (ok) v = sb[e];
+          f(v, ok);
+        }
       }
     } else {
       const int64_t chunk = bs * U;
@@ -166,7 +214,10 @@ TSA_DEV void walk(const Geom& g, F& f) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int64_t j = cb + u * bs + threadIdx.x;
-          if (j < g.v1) f(sb[j], true);
+          const bool ok = j < g.v1;
+          T v = (T)0;
+          if (ok) v = sb[j];
+          f(v, ok);
         }
         f.chunk();
       }
