@@ -10,10 +10,11 @@
 //   t in [2 T1, 3 T1) phase 3 (rare): last key digit of tile t - 2 T1
 // The block that finishes the last tile of a box's phase runs that box's
 // epilogue (merge, digit selection, next-phase set-up).  A phase-2 tile waits
-// for its box's phase-1 epilogue; phase-3 tickets wait until every box has
-// finished phase 2.  Tickets are handed out in increasing order, so every
-// wait is on tiles already taken by running blocks that never wait on
-// anything later: the kernel needs no co-resident grid and cannot deadlock.
+// for its box's phase-1 epilogue; a phase-3 tile skips at once unless phase 1
+// left its box without a candidate copy, and then waits for the box's phase-2
+// epilogue.  Tickets are handed out in increasing order, so every wait is on
+// tiles already taken by running blocks that never wait on anything later:
+// the kernel needs no co-resident grid and cannot deadlock.
 // Every wait is bounded; a block that gives up raises an error word and the
 // boxes left unfinished report TSA_EDEVICE.
 #include <math.h>
@@ -46,7 +47,7 @@ struct QGeom {
 
 struct QState {
   uint32_t done1, done2, done3;
-  uint32_t p1_ready;
+  uint32_t p1_ready, p2_ready;
   uint32_t skip2, need3, compact, cand_base, cand_n, cand_fill;
   uint32_t prefix, hist_ok, var_on, finished;
   float lo, hi, scale, shift;
@@ -56,7 +57,7 @@ struct QState {
 struct BatchHdr {
   uint64_t T1;
   uint64_t ticket;
-  uint32_t p2_done, any3, pool_top, err;
+  uint32_t pool_top, err;
   uint32_t nq, pad;
 };
 
@@ -142,7 +143,6 @@ __global__ void k_bplan(BArgs a) {
     g.ntiles = 0;
     res.status = TSA_EINVAL;
     res.flags = TSA_FLAG_BAD_REGION;
-    atomicAdd(&a.hdr->p2_done, 1u);  // nothing to wait for
   }
   a.geom[q] = g;
   QState s;
@@ -454,14 +454,13 @@ TSA_DEV void epilogue2(const BArgs& a, uint32_t q, BShared& sh, uint32_t* lds) {
         s.k = k2;
         s.need3 = 1;
         R.flags |= TSA_FLAG_PHASE3;
-        __hip_atomic_store(&a.hdr->any3, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
   }
-  __syncthreads();
+  __syncthreads();  // every thread's clearing of the digit counts precedes the release below
   if (t == 0) {
     __threadfence();
-    atomicAdd(&a.hdr->p2_done, 1u);
+    __hip_atomic_store(&s.p2_ready, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
 }
@@ -550,8 +549,7 @@ __global__ __launch_bounds__(kBBlock) void k_batch(BArgs a) {
     } else {
       phase = 3;
       lt = tk - 2 * T1;
-      if (!block_wait_ge(&a.hdr->p2_done, (uint32_t)a.nq, &a.hdr->err, sh)) return;
-      if (__hip_atomic_load(&a.hdr->any3, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0 || lt >= T1) return;
+      if (lt >= T1) return;  // every ticket handed out
     }
     // ticket -> (query, tile).  Tiles are taken box after box, so each box
     // finishes its phase early and its next-phase tiles seldom wait for it.
@@ -617,6 +615,14 @@ __global__ __launch_bounds__(kBBlock) void k_batch(BArgs a) {
         }
       }
     } else {
+      // only a box left without a candidate copy can need the last digit
+      if (!block_wait_ge(&s.p1_ready, 1u, &a.hdr->err, sh)) return;
+      if (t == 0) sh.flag = (DT == 0 && s.skip2 == 0 && s.compact == 0) ? 1u : 0u;
+      __syncthreads();
+      const bool may3 = sh.flag != 0;
+      __syncthreads();
+      if (!may3) continue;
+      if (!block_wait_ge(&s.p2_ready, 1u, &a.hdr->err, sh)) return;
       if (t == 0) sh.flag = s.need3;
       __syncthreads();
       const bool need3 = sh.flag != 0;
