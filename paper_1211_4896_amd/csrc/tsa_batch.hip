@@ -228,7 +228,10 @@ TSA_DEV bool block_wait_ge(const uint32_t* p, uint32_t v, uint32_t* err, BShared
     uint32_t ok = 0;
     const uint64_t t0 = wall_clock64();
     for (uint32_t it = 0; it < kSpinLimit; ++it) {
-      if (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= v) {
+      // relaxed polls, one acquire once the value is there (an agent-scope
+      // acquire invalidates this XCD's L2)
+      if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= v) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         ok = 1;
         break;
       }
@@ -375,7 +378,6 @@ TSA_DEV void epilogue1(const BArgs& a, uint32_t q, BShared& sh, uint32_t* lds) {
   __syncthreads();  // every thread's clearing of the digit counts precedes the release below
   if (t == 0) {
     s.skip2 = skip2 ? 1u : 0u;
-    __threadfence();
     __hip_atomic_store(&s.p1_ready, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
@@ -459,7 +461,6 @@ TSA_DEV void epilogue2(const BArgs& a, uint32_t q, BShared& sh, uint32_t* lds) {
   }
   __syncthreads();  // every thread's clearing of the digit counts precedes the release below
   if (t == 0) {
-    __threadfence();
     __hip_atomic_store(&s.p2_ready, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
@@ -642,11 +643,15 @@ __global__ __launch_bounds__(kBBlock) void k_batch(BArgs a) {
     // count the tile; the block finishing the last one runs the epilogue
     __syncthreads();
     if (t == 0) {
-      __threadfence();  // publish this tile's partial before counting it
+      // the release publishes this tile's partial and counters (the block's
+      // writes precede it through the barrier above); only the block that
+      // counts the last tile acquires, since only it reads the others' work.
+      // Each agent-scope release writes back this XCD's L2 and each acquire
+      // invalidates it, so a tile pays one of the first and none of the second.
       uint32_t* cnt = phase == 1 ? &s.done1 : phase == 2 ? &s.done2 : &s.done3;
-      const uint32_t prev = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      const uint32_t prev = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       sh.last = prev + 1 == g.ntiles ? 1u : 0u;
-      if (sh.last) __threadfence();  // the epilogue reads every tile's partial
+      if (sh.last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
     if (sh.last) {
