@@ -569,7 +569,7 @@ TSA_DEV void cand_copy_out(const CandSink& k, uint32_t fill) {
   __builtin_amdgcn_wave_barrier();  // the staged writes of every lane come first
   uint32_t g = 0;
   if (lane == 0) g = atomicAdd(k.counter, fill);
-  g = __shfl(g, 0);
+  g = __builtin_amdgcn_readfirstlane(g);  // lane 0's result, without an LDS permute
   for (uint32_t i = lane; i < fill; i += kWave)
     if (g + i < k.cap) k.list[g + i] = k.buf[w * kWaveStage + i];
   __builtin_amdgcn_wave_barrier();  // and the reads finish before the stage is refilled
