@@ -27,7 +27,6 @@
 namespace tsa {
 
 constexpr uint32_t kDefTileUnits = 16384;  // 16-byte vectors per tile (64K float32 voxels)
-constexpr uint32_t kDefCandMax = 1u << 20;  // largest first-digit bucket copied out
 constexpr uint32_t kPoolPerQuery = 16384;   // candidate pool keys per query (shared by the batch)
 constexpr int kBBlock = 256;
 #ifndef TSA_BATCH_UNROLL
@@ -846,7 +845,7 @@ static int enqueue_region_batch(const tsa_cube* cube, const tsa_region* d_region
   if (!d_ws || ws_bytes < L.total) return TSA_ENOMEM;
   DevInfo dev;
   if ((st = device_info(&dev))) return st;
-  uint32_t tile_units = kDefTileUnits, cand_max = kDefCandMax;
+  uint32_t tile_units = kDefTileUnits, cand_max = kBatchCandMax;
   int bpc = 4;
   if (tune) {
     if (tune->tile_voxels >= 1024) tile_units = (uint32_t)tune->tile_voxels / (cube->dtype == TSA_F32 ? 4 : 8);

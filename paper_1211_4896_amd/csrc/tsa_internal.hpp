@@ -18,6 +18,9 @@ namespace tsa {
 constexpr int kUnroll = 4;            // 16-byte loads in flight per lane
 constexpr uint32_t kTileUnits = 8192; // vectors per rows tile (single-region calls)
 constexpr int kMaxBlocks = 8192;      // upper bound of a pass grid (moment partial slots)
+// region batch: largest first-digit bucket whose keys a box copies out (larger ones
+// take a third pass over the box); the epilogue scans the copy with one block
+constexpr uint32_t kBatchCandMax = 1u << 20;
 
 struct Tuning {
   int block = 512;     // threads per block of the streaming passes

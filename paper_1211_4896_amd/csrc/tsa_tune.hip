@@ -77,10 +77,11 @@ int tsa_tune_region_batch(const tsa_cube* cube, const tsa_region* d_regions, int
   const int32_t tiles[] = {65536, 262144, 1048576};
   const int32_t bpcs[] = {2, 4, 6, 8};
   float bms = 1e30f;
-  tsa_tune bt = {65536, 256, 4, 65536};
+  const int32_t cm = (int32_t)kBatchCandMax;
+  tsa_tune bt = {65536, 256, 4, cm};
   for (int32_t tv : tiles) {
     for (int32_t bpc : bpcs) {
-      tsa_tune t = {tv, 256, bpc, 65536};
+      tsa_tune t = {tv, 256, bpc, cm};
       st = run_region_batch(cube, d_regions, nq, nbins, d_results, d_hists, &t, d_ws, ws_bytes, stream);  // warm
       if (st) break;
       (void)hipEventRecord(e0, s);
