@@ -18,9 +18,8 @@ HIPCC_FLAGS = [
     "-std=c++17",
     "-fPIC",
     "-shared",
-    # IEEE single precision exactly as written: no contraction into FMA,
-    # denormals kept (the histogram bin formula and the float-float sums
-    # depend on both)
+    # IEEE arithmetic exactly as written: no contraction into FMA (the
+    # histogram bin formula), denormals kept (bins and sums of denormal values)
     "-ffp-contract=off",
     "-fno-gpu-flush-denormals-to-zero",
     # no packed FP32 instructions

@@ -31,11 +31,9 @@ struct Elt<1> {
 };
 
 // ---- moments (Section 4.2): count, min/max keys, sum and sum of squares -------
-// float32: each lane keeps sum x and sum x^2 as an unevaluated float pair
-// (hi + lo).  Every addition is split exactly by TwoSum; the rounding error
-// goes to lo.  x^2 is split exactly by an FMA.  NaN and masked lanes add 0.
-// COUNT = false: the caller supplies the count (a pass that also builds the
-// first-digit histogram of the valid values has it as the histogram's total).
+// NaN and masked lanes add 0.  COUNT = false: the caller supplies the count (a
+// pass that also builds the first-digit histogram of the valid values has it
+// as the histogram's total).
 template <int DT, bool COUNT = true>
 struct MomAcc;
 
@@ -43,7 +41,8 @@ struct MomAcc;
 // exact in double (a float32 square needs 48 significand bits and lies in
 // [2^-298, 2^256]), so every step rounds once, with relative error 2^-53.
 // gfx950 issues double adds and fused multiply-adds at the single-precision
-// rate, which makes this both cheaper and more accurate than float-float sums.
+// rate, which makes this both cheaper and more accurate than float pairs
+// carrying their rounding errors (TwoSum and FMA splits).
 template <bool COUNT>
 struct MomAcc<0, COUNT> {
   double s = 0.0, q = 0.0;
