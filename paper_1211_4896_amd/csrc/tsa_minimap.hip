@@ -263,9 +263,8 @@ struct MMArgs {
 struct MMShared {
   MomShared mom;
   Partial part;
-  uint64_t wsum[kMMBlock / kWave];
-  uint32_t found, sel_digit;
-  uint64_t sel_cum, sel_bucket;
+  uint32_t wsum32[16];
+  uint32_t found, sel_digit, sel_cum32, sel_bucket32;
   // the cell's parameters, set by thread 0
   uint64_t cnt, k;
   uint32_t kmin, kmax, prefix, go;
@@ -415,9 +414,9 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
   if (sh.go) {
     // 2. first digit; histogram over [min, max] + second digit (+ M2 about the mean)
     uint32_t d1, d2, d3;
-    uint64_t cum, bucket;
-    bool found = block_select_u32(dig, kBins1, sh.k, sh, &d1, &cum, &bucket);
-    uint64_t k = sh.k - cum;
+    uint32_t cum, bucket;  // a cell holds fewer than 2^32 voxels
+    bool found = block_select_small(dig, kBins1, (uint32_t)sh.k, sh, &d1, &cum, &bucket);
+    uint32_t k = (uint32_t)sh.k - cum;
     for (uint32_t i = t; i < kBins2; i += kMMBlock) dig[i] = 0u;
     __syncthreads();
     HistOwnAcc hacc{hist, sh.lo, sh.scale, a.nbins - 1, a.rshift, (uint32_t)t & ((1u << a.rshift) - 1u)};
@@ -440,7 +439,7 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
       R.m2 = m2;
       R.std = sqrt(m2 / n);
     }
-    found = block_select_u32(dig, kBins2, k, sh, &d2, &cum, &bucket) && found;
+    found = block_select_small(dig, kBins2, k, sh, &d2, &cum, &bucket) && found;
     k -= cum;
     const uint32_t prefix = (d1 << kShift1) | (d2 << kShift2);
     // 3. last 8 bits over the keys of the second-digit bucket
@@ -453,7 +452,7 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
       lds_inc_rare(dig, x[j] == x[j] && (key >> kShift2) == p2, key & 0xFFu);
     }
     __syncthreads();
-    found = block_select_u32(dig, kBins3, k, sh, &d3, &cum, &bucket) && found;
+    found = block_select_small(dig, kBins3, k, sh, &d3, &cum, &bucket) && found;
     if (t == 0) {
       if (found)
         R.median = bvalue_of_key(prefix | d3, 0);

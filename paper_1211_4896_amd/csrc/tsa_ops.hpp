@@ -470,6 +470,66 @@ TSA_DEV bool block_select_u32(const uint32_t* hist, int nb, uint64_t k, SH& sh, 
   return found;
 }
 
+// Wave-wide inclusive prefix sum of 32-bit values: Hillis-Steele steps of 1,
+// 2, 4 and 8 lanes inside each row of 16 (DPP row shifts; a lane with no
+// source adds 0), then lane 15 of rows 0 and 2 added to rows 1 and 3, then
+// lane 31 added to rows 2 and 3 (DPP row broadcasts).
+TSA_DEV uint32_t wave_scan_incl_u32(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);  // row_shr:1
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);  // row_shr:2
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);  // row_shr:4
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);  // row_shr:8
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row_bcast:31
+  return v;
+}
+
+// block_select_u32 for histograms whose total fits in 32 bits (a mini-map
+// cell): 32-bit DPP scans instead of 64-bit shuffles, and every wave total
+// read at once.  SH provides wsum32[16], found, sel_digit, sel_cum32 and
+// sel_bucket32 in LDS; blockDim.x is at most 1024.
+template <class SH>
+TSA_DEV bool block_select_small(const uint32_t* hist, int nb, uint32_t k, SH& sh, uint32_t* digit,
+                                uint32_t* cum_before, uint32_t* bucket) {
+  const int t = threadIdx.x, bs = blockDim.x;
+  const int per = (nb + bs - 1) / bs;
+  const int b0 = t * per;
+  uint32_t local = 0;
+  for (int i = 0; i < per; ++i)
+    if (b0 + i < nb) local += hist[b0 + i];
+  const int lane = t % kWave, w = t / kWave;
+  const uint32_t inc = wave_scan_incl_u32(local);
+  if (lane == kWave - 1) sh.wsum32[w] = inc;
+  if (t == 0) sh.found = 0;
+  __syncthreads();
+  uint32_t base = inc - local;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) base += (i < w) ? sh.wsum32[i] : 0u;  // waves below this one
+  if (local > 0 && k >= base && k - base < local) {
+    uint32_t cum = base;
+    int d = b0;
+    for (int i = 0; i < per; ++i) {
+      const uint32_t h = (b0 + i < nb) ? hist[b0 + i] : 0u;
+      if (k - cum < h) {
+        d = b0 + i;
+        break;
+      }
+      cum += h;
+    }
+    sh.sel_digit = (uint32_t)d;
+    sh.sel_cum32 = cum;
+    sh.sel_bucket32 = hist[d];
+    sh.found = 1;
+  }
+  __syncthreads();
+  const bool found = sh.found != 0;
+  *digit = sh.sel_digit;
+  *cum_before = sh.sel_cum32;
+  *bucket = sh.sel_bucket32;
+  __syncthreads();
+  return found;
+}
+
 TSA_DEV double bvalue_of_key(uint32_t k, int dtype) {
   return dtype == 0 ? (double)__uint_as_float(f32bits_of_key(k)) : (double)i16_of_key(k);
 }
