@@ -194,12 +194,9 @@ __global__ __launch_bounds__(1024) void k_bscan(BArgs a) {
 struct BShared {
   uint64_t t;
   uint32_t q, tile, last, flag;
-  uint64_t u64a, u64b;
   MomShared mom;
-  uint64_t wsum[16];
-  uint32_t found;
-  uint32_t sel_digit;
-  uint64_t sel_cum, sel_bucket;
+  uint32_t wsum32[16];
+  uint32_t found, sel_digit, sel_cum32, sel_bucket32;
 };
 
 // The epilogues' per-thread merge arrays live in the dynamic LDS, past the
@@ -332,10 +329,9 @@ TSA_DEV void epilogue1(const BArgs& a, uint32_t q, BShared& sh, uint32_t* lds) {
   }
   skip2 = cnt == 0 || kmin == kmax;
   if (!skip2) {
-    const uint64_t k = (cnt - 1) / 2;
-    uint32_t d;
-    uint64_t cum, bucket;
-    const bool found = block_select_u32(dig, kBins1, k, sh, &d, &cum, &bucket);
+    const uint32_t k = (uint32_t)((cnt - 1) / 2);  // a box holds fewer than 2^32 voxels
+    uint32_t d, cum, bucket;
+    const bool found = block_select_small(dig, kBins1, k, sh, &d, &cum, &bucket);
     // the first-digit counts become the second-digit counts: clear them
     for (int i = t; i < kBins1; i += bs) a.digits[(size_t)q * kBins1 + i] = 0u;
     if (t == 0) {
@@ -411,11 +407,10 @@ TSA_DEV void epilogue2(const BArgs& a, uint32_t q, BShared& sh, uint32_t* lds) {
       __syncthreads();
     }
     uint32_t* dig = a.digits + (size_t)q * kBins1;
-    uint32_t d;
-    uint64_t cum, bucket;
-    bool found = block_select_u32(dig, kBins2, s.k, sh, &d, &cum, &bucket);
+    uint32_t d, cum, bucket;
+    bool found = block_select_small(dig, kBins2, (uint32_t)s.k, sh, &d, &cum, &bucket);
     const uint32_t prefix = s.prefix | (d << kShift2);
-    const uint64_t k2 = s.k - cum;
+    const uint32_t k2 = (uint32_t)s.k - cum;
     if (!found) {
       if (t == 0) {
         R.status = TSA_EDEVICE;
@@ -438,9 +433,8 @@ TSA_DEV void epilogue2(const BArgs& a, uint32_t q, BShared& sh, uint32_t* lds) {
         if ((key >> kShift2) == p2) lds_inc(lds, key & 0xFFu);
       }
       __syncthreads();
-      uint32_t d3;
-      uint64_t cum3, b3;
-      found = block_select_u32(lds, kBins3, k2, sh, &d3, &cum3, &b3);
+      uint32_t d3, cum3, b3;
+      found = block_select_small(lds, kBins3, k2, sh, &d3, &cum3, &b3);
       if (t == 0) {
         if (found)
           R.median = bvalue_of_key(prefix | d3, DT);
@@ -468,9 +462,8 @@ TSA_DEV void epilogue2(const BArgs& a, uint32_t q, BShared& sh, uint32_t* lds) {
 template <int DT>
 TSA_DEV void epilogue3(const BArgs& a, uint32_t q, BShared& sh) {
   QState& s = a.st[q];
-  uint32_t d;
-  uint64_t cum, bucket;
-  const bool found = block_select_u32(a.digits + (size_t)q * kBins1, kBins3, s.k, sh, &d, &cum, &bucket);
+  uint32_t d, cum, bucket;
+  const bool found = block_select_small(a.digits + (size_t)q * kBins1, kBins3, (uint32_t)s.k, sh, &d, &cum, &bucket);
   if (threadIdx.x == 0) {
     if (found)
       a.results[q].median = bvalue_of_key(s.prefix | d, DT);
