@@ -544,7 +544,8 @@ struct PassB {
 };
 
 template <int DT, bool VEC, bool NT>
-__global__ __launch_bounds__(1024) void k_pass_b(Geom g, int32_t nbins, uint32_t rshift, SelState* __restrict__ st,
+__global__ __launch_bounds__(1024) void k_pass_b(Geom g, int32_t nbins, uint32_t rshift, uint32_t stage,
+                                                 SelState* __restrict__ st,
                                                  uint64_t* __restrict__ counts, uint64_t* __restrict__ outl,
                                                  uint64_t* __restrict__ hist2, uint32_t* __restrict__ cand,
                                                  Partial* __restrict__ parts2) {
@@ -560,7 +561,7 @@ __global__ __launch_bounds__(1024) void k_pass_b(Geom g, int32_t nbins, uint32_t
   const bool var_on = DT == 0 && st->var_on != 0;
   if (!hist_on && !sel_on && !var_on) return;
   lds_zero(lds, hsize + kBins2);
-  const CandSink sink = cand_sink_lds(l2 + kBins2, cand, &st->ncand, st->cand_cap);
+  const CandSink sink = cand_sink_lds(l2 + kBins2, stage, cand, &st->ncand, st->cand_cap);
   __syncthreads();
   PassB<DT> b{HistOwnAcc{lds, st->lo, st->scale, nbins - 1, rshift, threadIdx.x & ((1u << rshift) - 1u)},
               Level2Acc<DT>{l2, sel_on ? (st->prefix >> kShift1) : 0xFFFFFFFFu, sel_on && st->compact != 0, sink},
@@ -608,7 +609,7 @@ __global__ __launch_bounds__(1024) void k_pass_bwin(Geom g, int32_t nbins, SelSt
   const bool var_on = DT == 0 && st->var_on != 0;
   if (!hist_on && !sel_on && !var_on) return;
   lds_zero(lds, kWinBins + kBins2);
-  const CandSink sink = cand_sink_lds(l2 + kBins2, cand, &st->ncand, st->cand_cap);
+  const CandSink sink = cand_sink_lds(l2 + kBins2, kWaveStage, cand, &st->ncand, st->cand_cap);
   __syncthreads();
   const int32_t w0 = st->win0;
   PassBWin<DT> b{HistWinAcc{lds, st->lo, st->scale, nbins - 1, w0, counts},
@@ -1116,8 +1117,8 @@ int run_stats(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa
   int st = prepare(cube, region, d_ws, ws_bytes, stream, &P, kBpcStats);
   if (st) return st;
   const size_t budget = P.dev.lds_per_block < 65536 ? P.dev.lds_per_block : 65536;
-  const size_t cand_b = (size_t)(P.block / kWave) * kWaveStage * 4;  // pass B's candidate staging
-  const bool wide = ((size_t)nbins + kTrash + kBins2) * 4 + cand_b > budget;
+  const size_t cand_small = (size_t)(P.block / kWave) * kWaveStage * 4;  // pass B's candidate staging
+  const bool wide = ((size_t)nbins + kTrash + kBins2) * 4 + cand_small > budget;
   // 16-bit counters: (nbins+1)/2 words + level-2 digits, plus ~10 KB of static LDS
   const size_t lds16 = ((((size_t)nbins + 1) / 2) + kBins2) * 4;
   if (wide && lds16 + 10240 > P.dev.lds_per_block) return TSA_ENOTSUP;
@@ -1145,15 +1146,23 @@ int run_stats(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa
     // (its static LDS: candidate staging, moment reduction, outliers)
     const size_t per_block = P.dev.lds_per_block / (size_t)P.bpc;
     // (and within the 64 KB a launch takes without raising its LDS limit)
-    const size_t fixed_b = sizeof(MomShared) + 32 * 4 + cand_b + (kBins2 + kTrash) * 4 + 1024;  // + slack
     const size_t cap_b = per_block < budget ? per_block : budget;
+    auto fixed_of = [&](size_t cb) { return sizeof(MomShared) + 32 * 4 + cb + (kBins2 + kTrash) * 4 + 1024; };  // + slack
+    // the deep candidate stage when one replica of every bin still fits beside it
+    uint32_t stage = kWaveStageBig;
+    size_t cand_b = (size_t)(P.block / kWave) * stage * 4;
+    if (fixed_of(cand_b) + ((size_t)nbins + kTrash) * 4 > cap_b) {
+      stage = kWaveStage;
+      cand_b = cand_small;
+    }
+    const size_t fixed_b = fixed_of(cand_b);
     const size_t budget_b = cap_b > fixed_b ? cap_b - fixed_b : 0;
     uint32_t rsb = rep_shift_for(nbins, budget_b);
     const size_t ldsb = (((size_t)nbins << rsb) + kTrash + kBins2) * 4 + cand_b;
     TSA_TRACED("pass_b", P.s,
       TSA_DISPATCH(cube->dtype, P.vec, tuning().nt,
                    hipLaunchKernelGGL((k_pass_b<DT, VEC, NT>), dim3(P.grid), dim3(P.block), ldsb, P.s, P.g, nbins,
-                                      rsb, stp, d_counts, outl, h2, cand, parts2)));
+                                      rsb, stage, stp, d_counts, outl, h2, cand, parts2)));
   } else {
     // one 1024-thread block per compute unit: a window of 32-bit counters when
     // the device grants the LDS, else 16-bit counters flushed in epochs

@@ -593,33 +593,36 @@ struct Digit1Acc {  // top 12 key bits of every valid element
 // walkers call every accumulator from all lanes at the same points, so the
 // wave's fill count is an ordinary variable that every lane updates alike
 // (kept in a register, no LDS round trip per append).
-constexpr uint32_t kWaveStage = 128;  // staged keys per wave
+// A copy-out waits for its global atomic, so a deeper stage (fewer copy-outs)
+// pays where the LDS allows it.
+constexpr uint32_t kWaveStage = 128;     // staged keys per wave (default)
+constexpr uint32_t kWaveStageBig = 512;  // where the LDS has room
 constexpr int kMaxWaves = 16;
 
-// Staging of a block of NW waves.
-template <int NW>
+// Staging of a block of NW waves, S keys each.
+template <int NW, uint32_t S = kWaveStage>
 struct CandSharedN {
-  uint32_t buf[NW][kWaveStage];
+  uint32_t buf[NW][S];
 };
 using CandShared = CandSharedN<kMaxWaves>;
 
 struct CandSink {
-  uint32_t* buf;      // kWaveStage staged keys per wave
+  uint32_t* buf;      // `stage` staged keys per wave
   uint32_t* list;     // global list
   uint32_t* counter;  // global fill counter
   uint32_t cap;       // global capacity
+  uint32_t stage;     // keys per wave the stage holds
   uint32_t fill;      // keys this wave has staged (equal in every lane)
 };
 
-template <int NW>
-TSA_DEV CandSink cand_sink(CandSharedN<NW>& cs, uint32_t* list, uint32_t* counter, uint32_t cap) {
-  return CandSink{&cs.buf[0][0], list, counter, cap, 0u};
+template <int NW, uint32_t S>
+TSA_DEV CandSink cand_sink(CandSharedN<NW, S>& cs, uint32_t* list, uint32_t* counter, uint32_t cap) {
+  return CandSink{&cs.buf[0][0], list, counter, cap, S, 0u};
 }
 
-// Staging carved from dynamic LDS: kWaveStage words per wave of the block.
-TSA_DEV uint32_t cand_lds_words(uint32_t waves) { return waves * kWaveStage; }
-TSA_DEV CandSink cand_sink_lds(uint32_t* base, uint32_t* list, uint32_t* counter, uint32_t cap) {
-  return CandSink{base, list, counter, cap, 0u};
+// Staging carved from dynamic LDS: `stage` words per wave of the block.
+TSA_DEV CandSink cand_sink_lds(uint32_t* base, uint32_t stage, uint32_t* list, uint32_t* counter, uint32_t cap) {
+  return CandSink{base, list, counter, cap, stage, 0u};
 }
 
 // The wave copies its `fill` staged keys out (one global atomic).  Whole wave.
@@ -630,7 +633,7 @@ TSA_DEV void cand_copy_out(const CandSink& k, uint32_t fill) {
   if (lane == 0) g = atomicAdd(k.counter, fill);
   g = __builtin_amdgcn_readfirstlane(g);  // lane 0's result, without an LDS permute
   for (uint32_t i = lane; i < fill; i += kWave)
-    if (g + i < k.cap) k.list[g + i] = k.buf[w * kWaveStage + i];
+    if (g + i < k.cap) k.list[g + i] = k.buf[w * k.stage + i];
   __builtin_amdgcn_wave_barrier();  // and the reads finish before the stage is refilled
 }
 
@@ -640,12 +643,12 @@ TSA_DEV void cand_copy_out(const CandSink& k, uint32_t fill) {
 TSA_DEV void cand_append_slow(bool m, uint32_t key, uint64_t bal, CandSink& k) {
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const uint32_t n = (uint32_t)__popcll(bal);
-  if (k.fill + n > kWaveStage) {
+  if (k.fill + n > k.stage) {
     cand_copy_out(k, k.fill);
     k.fill = 0;
   }
   const uint32_t off = (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
-  if (m) k.buf[w * kWaveStage + k.fill + off] = key;
+  if (m) k.buf[w * k.stage + k.fill + off] = key;
   k.fill += n;
 }
 
