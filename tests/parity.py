@@ -44,7 +44,11 @@ def check_moments(got: dict, want: dict, dtype: str = "f32", what: str = ""):
     assert same_value(got["min"], want["min"], dtype), (what, "min", got["min"], want["min"])
     assert same_value(got["max"], want["max"], dtype), (what, "max", got["max"], want["max"])
     if not (math.isfinite(want["mean"]) and math.isfinite(want["std"])):
-        return  # infinities in the data: only NaN/inf-ness is compared
+        # infinities in the data: no finite spread exists; unless every value
+        # is the same (std 0 by definition), the kernels report it as NaN too
+        if want["min"] != want["max"] and math.isnan(want["std"]):
+            assert math.isnan(got["std"]) and math.isnan(got["m2"]), (what, "std", got["std"])
+        return
     rms = math.hypot(want["mean"], want["std"])
     assert abs(got["mean"] - want["mean"]) <= MEAN_REL * abs(want["mean"]) + MEAN_RMS * rms, \
         (what, "mean", got["mean"], want["mean"])
