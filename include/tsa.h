@@ -97,10 +97,14 @@ typedef enum {
   TSA_OP_MAD = 6
 } tsa_op;
 
-/* Tunables of tsa_region_batch (NULL = the library's tuned choice). */
+/* Tunables of tsa_region_batch (NULL = the autotuner's remembered choice for
+ * the batch's shape, else the defaults: automatic tiles, 4 blocks per CU,
+ * 2^20-key candidate cap). */
 typedef struct {
-  int32_t tile_voxels;     /* target voxels per work item (power of two, >= 1024) */
-  int32_t block_threads;   /* 256 or 512 */
+  int32_t tile_voxels;     /* target voxels per work item (>= 1024); below 1024: chosen on the
+                              device so the batch makes about four tiles per persistent block,
+                              16K to 1M voxels each */
+  int32_t block_threads;   /* 0 or 256 (the batch kernel's block size; others: TSA_ENOTSUP) */
   int32_t blocks_per_cu;   /* persistent blocks per compute unit, >= 1 */
   int32_t cand_max;        /* largest bucket compacted for the median's last digits */
 } tsa_tune;

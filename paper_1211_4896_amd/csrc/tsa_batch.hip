@@ -26,7 +26,6 @@
 
 namespace tsa {
 
-constexpr uint32_t kDefTileUnits = 16384;  // 16-byte vectors per tile (64K float32 voxels)
 constexpr uint32_t kPoolPerQuery = 16384;   // candidate pool keys per query (shared by the batch)
 constexpr int kBBlock = 256;
 #ifndef TSA_BATCH_UNROLL
@@ -57,7 +56,7 @@ struct BatchHdr {
   uint64_t T1;
   uint64_t ticket;
   uint32_t pool_top, err;
-  uint32_t nq, pad;
+  uint32_t nq, tile_units;  // tile_units: chosen on the device when the caller set none
 };
 
 struct BArgs {
@@ -65,7 +64,8 @@ struct BArgs {
   int64_t nx, ny, nz;
   const tsa_region* regions;
   int32_t nq, nbins;
-  uint32_t rshift, tile_units, max_tiles, cand_max, pool_keys;
+  uint32_t rshift, tile_units, max_tiles, cand_max, pool_keys;  // tile_units 0: chosen on the device
+  uint32_t grid;  // persistent blocks
   int32_t vec;
   tsa_result* results;
   uint64_t* hists;
@@ -83,6 +83,42 @@ struct BArgs {
 // ---------------------------------------------------------------------------
 // planning
 // ---------------------------------------------------------------------------
+
+// Tile size when the caller chose none: the batch's units (16-byte vectors,
+// or elements on the scalar path) spread over about four tiles per persistent
+// block, within [kAutoMinVoxels, kAutoMaxVoxels] voxels per tile: small
+// batches cut their few boxes finely enough to fill the GPU, large ones keep
+// the per-tile zeroing, flushing and counting rare.
+constexpr uint32_t kAutoMinVoxels = 16384, kAutoMaxVoxels = 1u << 20;
+
+template <int DT>
+__global__ __launch_bounds__(1024) void k_bauto(BArgs a) {
+  __shared__ uint64_t part[16];
+  const int t = threadIdx.x;
+  const int64_t epv = DT == 0 ? 4 : 8;
+  uint64_t local = 0;
+  for (int q = t; q < a.nq; q += blockDim.x) {
+    const tsa_region r = a.regions[q];
+    if (!(r.x0 >= 0 && r.y0 >= 0 && r.z0 >= 0 && r.x1 <= a.nx && r.y1 <= a.ny && r.z1 <= a.nz && r.x0 < r.x1 &&
+          r.y0 < r.y1 && r.z0 < r.z1))
+      continue;
+    const uint64_t row = a.vec ? (uint64_t)((r.x1 + epv - 1) / epv - r.x0 / epv) : (uint64_t)(r.x1 - r.x0);
+    local += row * (uint64_t)(r.y1 - r.y0) * (uint64_t)(r.z1 - r.z0);
+  }
+  local = wave_sum_u64(local);
+  if (t % kWave == 0) part[t / kWave] = local;
+  __syncthreads();
+  if (t == 0) {
+    uint64_t total = 0;
+    for (int i = 0; i < (int)(blockDim.x / kWave); ++i) total += part[i];
+    const uint64_t per_unit = a.vec ? (uint64_t)epv : 1u;  // voxels per unit
+    const uint64_t lo = kAutoMinVoxels / per_unit, hi = kAutoMaxVoxels / per_unit;
+    uint64_t tu = total / (4ull * a.grid);
+    if (tu < lo) tu = lo;
+    if (tu > hi) tu = hi;
+    a.hdr->tile_units = (uint32_t)tu;
+  }
+}
 
 template <int DT>
 __global__ void k_bplan(BArgs a) {
@@ -121,7 +157,8 @@ __global__ void k_bplan(BArgs a) {
         g.head_skip = 0;
         g.last_valid = 1;
       }
-      uint64_t rpt = a.tile_units / g.vpr;
+      const uint32_t tu = a.tile_units ? a.tile_units : a.hdr->tile_units;
+      uint64_t rpt = tu / g.vpr;
       if (rpt < 1) rpt = 1;
       uint64_t nt = (g.nrows + rpt - 1) / rpt;
       if (nt > a.max_tiles) {
@@ -838,7 +875,7 @@ static int enqueue_region_batch(const tsa_cube* cube, const tsa_region* d_region
   if (!d_ws || ws_bytes < L.total) return TSA_ENOMEM;
   DevInfo dev;
   if ((st = device_info(&dev))) return st;
-  uint32_t tile_units = kDefTileUnits, cand_max = kBatchCandMax;
+  uint32_t tile_units = 0, cand_max = kBatchCandMax;  // 0: chosen on the device from the batch's volume
   int bpc = 4;
   if (tune) {
     if (tune->tile_voxels >= 1024) tile_units = (uint32_t)tune->tile_voxels / (cube->dtype == TSA_F32 ? 4 : 8);
@@ -846,7 +883,7 @@ static int enqueue_region_batch(const tsa_cube* cube, const tsa_region* d_region
     if (tune->cand_max >= 0) cand_max = (uint32_t)tune->cand_max;
     if (tune->block_threads != 0 && tune->block_threads != kBBlock) return TSA_ENOTSUP;
   }
-  if (tile_units < 256) tile_units = 256;
+  if (tile_units && tile_units < 256) tile_units = 256;
   const int epv = cube->dtype == TSA_F32 ? 4 : 8;
   const bool vec = ((uintptr_t)cube->data % 16) == 0 && (cube->nx % epv) == 0;
   if (!vec) tile_units *= (uint32_t)epv;  // scalar units are elements
@@ -861,6 +898,7 @@ static int enqueue_region_batch(const tsa_cube* cube, const tsa_region* d_region
   a.nbins = nbins;
   a.rshift = nbins <= 1024 ? 2u : nbins <= 2048 ? 1u : 0u;
   a.tile_units = tile_units;
+  a.grid = (uint32_t)(dev.cus * bpc);
   a.max_tiles = L.max_tiles;
   a.cand_max = cand_max;
   a.pool_keys = L.pool_keys;
@@ -884,12 +922,18 @@ static int enqueue_region_batch(const tsa_cube* cube, const tsa_region* d_region
   bfill(a.digits, (size_t)kBins1 * nq, s);
   bfill(d_hists, (size_t)nbins * nq * 2, s);
   const int pb = (nq + 255) / 256;
+  if (!a.tile_units) {
+    if (cube->dtype == TSA_F32)
+      TSA_TRACED("batch_auto", s, hipLaunchKernelGGL(k_bauto<0>, dim3(1), dim3(1024), 0, s, a));
+    else
+      TSA_TRACED("batch_auto", s, hipLaunchKernelGGL(k_bauto<1>, dim3(1), dim3(1024), 0, s, a));
+  }
   if (cube->dtype == TSA_F32)
     TSA_TRACED("batch_plan", s, hipLaunchKernelGGL(k_bplan<0>, dim3(pb), dim3(256), 0, s, a));
   else
     TSA_TRACED("batch_plan", s, hipLaunchKernelGGL(k_bplan<1>, dim3(pb), dim3(256), 0, s, a));
   TSA_TRACED("batch_scan", s, hipLaunchKernelGGL(k_bscan, dim3(1), dim3(1024), 0, s, a));
-  const int grid = dev.cus * bpc;
+  const int grid = (int)a.grid;
   if (cube->dtype == TSA_F32) {
     if (vec)
       TSA_TRACED("batch", s, hipLaunchKernelGGL((k_batch<0, true, true>), dim3(grid), dim3(kBBlock), lds, s, a));
