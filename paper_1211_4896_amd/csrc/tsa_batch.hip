@@ -288,6 +288,16 @@ TSA_DEV bool block_wait_ge(const uint32_t* p, uint32_t v, uint32_t* err, BShared
   return ok;
 }
 
+// Every wave waits until its own global stores and atomics are acknowledged
+// (s_waitcnt vmcnt(0)) before the barrier after which one thread publishes
+// the block's work with an agent-scope release: a workgroup barrier alone
+// does not wait for other waves' writes to reach the L2 that the release
+// writes back.
+TSA_DEV void block_writes_done() {
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt 0; expcnt and lgkmcnt not waited for
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // epilogues (whole block)
 // ---------------------------------------------------------------------------
@@ -407,7 +417,7 @@ TSA_DEV void epilogue1(const BArgs& a, uint32_t q, BShared& sh, uint32_t* lds) {
       }
     }
   }
-  __syncthreads();  // every thread's clearing of the digit counts precedes the release below
+  block_writes_done();  // every thread's clearing of the digit counts precedes the release below
   if (t == 0) {
     s.skip2 = skip2 ? 1u : 0u;
     __hip_atomic_store(&s.p1_ready, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -489,7 +499,7 @@ TSA_DEV void epilogue2(const BArgs& a, uint32_t q, BShared& sh, uint32_t* lds) {
       }
     }
   }
-  __syncthreads();  // every thread's clearing of the digit counts precedes the release below
+  block_writes_done();  // every thread's clearing of the digit counts precedes the release below
   if (t == 0) {
     __hip_atomic_store(&s.p2_ready, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }
@@ -670,7 +680,7 @@ __global__ __launch_bounds__(kBBlock) void k_batch(BArgs a) {
       }
     }
     // count the tile; the block finishing the last one runs the epilogue
-    __syncthreads();
+    block_writes_done();
     if (t == 0) {
       // the release publishes this tile's partial and counters (the block's
       // writes precede it through the barrier above); only the block that
