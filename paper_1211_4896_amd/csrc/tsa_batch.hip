@@ -768,16 +768,13 @@ static int enqueue_region_batch(const tsa_cube* cube, const tsa_region* d_region
 bool tune_lookup(const tsa_cube* cube, int32_t nbins, int32_t nq, tsa_tune* out);
 
 // ---- graph cache -------------------------------------------------------------
-// The launch sequence of one argument set (clears, plan, scan, persistent
-// kernel, final check) is captured once into a HIP graph on a private stream
-// and replayed on the caller's stream afterwards.  Entries are keyed by every
-// argument; the cache keeps the most recent kGraphCap of them.
+// A launch sequence of one argument set (clears, plan, scan, persistent
+// kernel, final check; or the passes of tsa_stats) is captured once into a HIP
+// graph on a private stream and replayed on the caller's stream afterwards.
+// Entries are keyed by every argument; the cache keeps the most recent
+// kGraphCap of them.
 namespace {
 constexpr size_t kGraphCap = 256;
-struct GraphKey {
-  uintptr_t v[16];
-  bool operator==(const GraphKey& o) const { return memcmp(v, o.v, sizeof(v)) == 0; }
-};
 struct GraphEntry {
   GraphKey key;
   hipGraphExec_t exec;
@@ -786,12 +783,17 @@ struct GraphEntry {
 struct GraphCache {
   std::mutex mu;
   std::vector<GraphEntry> entries;
+  std::vector<GraphKey> seen;  // argument sets launched once, directly (most recent kSeenCap)
   uint64_t clock = 0;
 };
+constexpr size_t kSeenCap = 1024;
 GraphCache& graphs() {
   static GraphCache g;
   return g;
 }
+bool same_key(const GraphKey& a, const GraphKey& b) { return memcmp(a.v, b.v, sizeof(a.v)) == 0; }
+}  // namespace
+
 bool graphs_enabled() {
   static const bool on = [] {
     const char* e = getenv("TSA_GRAPH");
@@ -799,57 +801,31 @@ bool graphs_enabled() {
   }();
   return on;
 }
-}  // namespace
 
-int run_region_batch(const tsa_cube* cube, const tsa_region* d_regions, int32_t nq, int32_t nbins,
-                     tsa_result* d_results, uint64_t* d_hists, const tsa_tune* tune, void* d_ws, size_t ws_bytes,
-                     tsa_stream_t stream) {
-  int st = check_cube(cube);
-  if (st) return st;
-  if (!d_regions || !d_results || !d_hists || nq < 1 || nq > kMaxQueries || nbins < 1 || nbins > 4096)
-    return TSA_EINVAL;
-  if (!d_ws || ws_bytes < batch_layout(nq).total) return TSA_ENOMEM;
-  hipStream_t s = (hipStream_t)stream;
-  tsa_tune tuned;
-  if (!tune && tune_lookup(cube, nbins, nq, &tuned)) tune = &tuned;
-  if (!graphs_enabled() || trace_active())
-    return enqueue_region_batch(cube, d_regions, nq, nbins, d_results, d_hists, tune, d_ws, ws_bytes, s);
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return TSA_EDEVICE;
-  GraphKey key;
-  memset(&key, 0, sizeof(key));
-  key.v[0] = (uintptr_t)cube->data;
-  key.v[1] = (uintptr_t)cube->dtype;
-  key.v[2] = (uintptr_t)cube->nx;
-  key.v[3] = (uintptr_t)cube->ny;
-  key.v[4] = (uintptr_t)cube->nz;
-  key.v[5] = (uintptr_t)d_regions;
-  key.v[6] = (uintptr_t)nq;
-  key.v[7] = (uintptr_t)nbins;
-  key.v[8] = (uintptr_t)d_results;
-  key.v[9] = (uintptr_t)d_hists;
-  key.v[10] = (uintptr_t)d_ws;
-  key.v[11] = (uintptr_t)ws_bytes;
-  key.v[12] = (uintptr_t)dev;
-  if (tune) {
-    key.v[13] = ((uintptr_t)(uint32_t)tune->tile_voxels << 32) | (uint32_t)tune->block_threads;
-    key.v[14] = ((uintptr_t)(uint32_t)tune->blocks_per_cu << 32) | (uint32_t)tune->cand_max;
-    key.v[15] = 1;
-  }
+int graph_run(const GraphKey& key, hipStream_t s, int (*enqueue)(void* ctx, hipStream_t), void* ctx) {
   GraphCache& G = graphs();
+  bool again = false;
   {
     std::lock_guard<std::mutex> g(G.mu);
     for (GraphEntry& e : G.entries) {
-      if (e.key == key) {
+      if (same_key(e.key, key)) {
         e.used = ++G.clock;
         return hipGraphLaunch(e.exec, s) == hipSuccess ? TSA_OK : TSA_EDEVICE;
       }
     }
+    // an argument set is captured the second time it comes: one-off calls
+    // (fresh buffers every time) launch directly and cost no capture
+    for (size_t i = 0; i < G.seen.size() && !again; ++i) again = same_key(G.seen[i], key);
+    if (!again) {
+      if (G.seen.size() >= kSeenCap) G.seen.erase(G.seen.begin());
+      G.seen.push_back(key);
+    }
   }
+  if (!again) return enqueue(ctx, s);
   thread_local hipStream_t cap = nullptr;
   if (!cap && hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return TSA_EDEVICE;
   if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return TSA_EDEVICE;
-  st = enqueue_region_batch(cube, d_regions, nq, nbins, d_results, d_hists, tune, d_ws, ws_bytes, cap);
+  const int st = enqueue(ctx, cap);
   hipGraph_t graph = nullptr;
   const bool ended = hipStreamEndCapture(cap, &graph) == hipSuccess;
   if (st != TSA_OK || !ended || !graph) {
@@ -872,6 +848,64 @@ int run_region_batch(const tsa_cube* cube, const tsa_region* d_regions, int32_t 
     G.entries.push_back(GraphEntry{key, exec, ++G.clock});
   }
   return hipGraphLaunch(exec, s) == hipSuccess ? TSA_OK : TSA_EDEVICE;
+}
+
+namespace {
+struct BatchCall {
+  const tsa_cube* cube;
+  const tsa_region* d_regions;
+  int32_t nq, nbins;
+  tsa_result* d_results;
+  uint64_t* d_hists;
+  const tsa_tune* tune;
+  void* d_ws;
+  size_t ws_bytes;
+};
+int enqueue_batch_call(void* ctx, hipStream_t s) {
+  const BatchCall& c = *(const BatchCall*)ctx;
+  return enqueue_region_batch(c.cube, c.d_regions, c.nq, c.nbins, c.d_results, c.d_hists, c.tune, c.d_ws,
+                              c.ws_bytes, s);
+}
+}  // namespace
+
+int run_region_batch(const tsa_cube* cube, const tsa_region* d_regions, int32_t nq, int32_t nbins,
+                     tsa_result* d_results, uint64_t* d_hists, const tsa_tune* tune, void* d_ws, size_t ws_bytes,
+                     tsa_stream_t stream) {
+  int st = check_cube(cube);
+  if (st) return st;
+  if (!d_regions || !d_results || !d_hists || nq < 1 || nq > kMaxQueries || nbins < 1 || nbins > 4096)
+    return TSA_EINVAL;
+  if (!d_ws || ws_bytes < batch_layout(nq).total) return TSA_ENOMEM;
+  hipStream_t s = (hipStream_t)stream;
+  tsa_tune tuned;
+  if (!tune && tune_lookup(cube, nbins, nq, &tuned)) tune = &tuned;
+  if (!graphs_enabled() || trace_active())
+    return enqueue_region_batch(cube, d_regions, nq, nbins, d_results, d_hists, tune, d_ws, ws_bytes, s);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return TSA_EDEVICE;
+  GraphKey key;
+  memset(&key, 0, sizeof(key));
+  key.v[0] = 1;  // the region batch
+  key.v[1] = (uintptr_t)cube->data;
+  key.v[2] = (uintptr_t)cube->dtype;
+  key.v[3] = (uintptr_t)cube->nx;
+  key.v[4] = (uintptr_t)cube->ny;
+  key.v[5] = (uintptr_t)cube->nz;
+  key.v[6] = (uintptr_t)d_regions;
+  key.v[7] = (uintptr_t)nq;
+  key.v[8] = (uintptr_t)nbins;
+  key.v[9] = (uintptr_t)d_results;
+  key.v[10] = (uintptr_t)d_hists;
+  key.v[11] = (uintptr_t)d_ws;
+  key.v[12] = (uintptr_t)ws_bytes;
+  key.v[13] = (uintptr_t)dev;
+  if (tune) {
+    key.v[14] = ((uintptr_t)(uint32_t)tune->tile_voxels << 32) | (uint32_t)tune->block_threads;
+    key.v[15] = ((uintptr_t)(uint32_t)tune->blocks_per_cu << 32) | (uint32_t)tune->cand_max;
+    key.v[16] = 1;
+  }
+  BatchCall c{cube, d_regions, nq, nbins, d_results, d_hists, tune, d_ws, ws_bytes};
+  return graph_run(key, s, enqueue_batch_call, &c);
 }
 
 static int enqueue_region_batch(const tsa_cube* cube, const tsa_region* d_regions, int32_t nq, int32_t nbins,

@@ -46,6 +46,16 @@ void trace_end(hipStream_t s);
     __VA_ARGS__;                 \
     ::tsa::trace_end(S);         \
   } while (0)
+// Launch sequences captured once into HIP graphs and replayed, keyed by every
+// argument of the call (unused slots zero).  TSA_GRAPH=0 disables them.
+struct GraphKey {
+  uintptr_t v[24];
+};
+bool graphs_enabled();
+// Replays the graph cached under key on s, or captures enqueue(ctx, stream)
+// on a private stream first; returns the capture's or the launch's status.
+int graph_run(const GraphKey& key, hipStream_t s, int (*enqueue)(void* ctx, hipStream_t), void* ctx);
+
 Magic make_magic(uint32_t d);
 int check_cube(const tsa_cube* c);
 int region_box(const tsa_cube* c, const tsa_region* r, tsa_region* b);

@@ -1109,8 +1109,67 @@ int run_median(const tsa_cube* cube, const tsa_region* region, tsa_result* d_out
   return launch_median_tail(cube, P, d_out, true);
 }
 
+static int enqueue_stats(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa_result* d_out,
+                         uint64_t* d_counts, uint64_t* d_outliers, void* d_ws, size_t ws_bytes, tsa_stream_t stream);
+
+namespace {
+struct StatsCall {
+  const tsa_cube* cube;
+  const tsa_region* region;
+  int32_t nbins;
+  tsa_result* d_out;
+  uint64_t* d_counts;
+  uint64_t* d_outliers;
+  void* d_ws;
+  size_t ws_bytes;
+};
+int enqueue_stats_call(void* ctx, hipStream_t s) {
+  const StatsCall& c = *(const StatsCall*)ctx;
+  return enqueue_stats(c.cube, c.region, c.nbins, c.d_out, c.d_counts, c.d_outliers, c.d_ws, c.ws_bytes, s);
+}
+}  // namespace
+
+// The fused trio's launches go out as one replayed graph (keyed by every
+// argument, the box's corners included), so the GPU does not wait on the host
+// between its short kernels; traced calls launch directly.
 int run_stats(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa_result* d_out, uint64_t* d_counts,
               uint64_t* d_outliers, void* d_ws, size_t ws_bytes, tsa_stream_t stream) {
+  // argument errors, tracing, and more bins than one LDS histogram holds (the
+  // wide passes set kernel attributes at launch) take the direct launch
+  int dev = 0;
+  if (check_cube(cube) != TSA_OK || !d_out || !d_counts || nbins < 1 || nbins > 8192 || !d_ws ||
+      !graphs_enabled() || trace_active() || hipGetDevice(&dev) != hipSuccess)
+    return enqueue_stats(cube, region, nbins, d_out, d_counts, d_outliers, d_ws, ws_bytes, stream);
+  GraphKey key;
+  memset(&key, 0, sizeof(key));
+  key.v[0] = 2;  // tsa_stats
+  key.v[1] = (uintptr_t)cube->data;
+  key.v[2] = (uintptr_t)cube->dtype;
+  key.v[3] = (uintptr_t)cube->nx;
+  key.v[4] = (uintptr_t)cube->ny;
+  key.v[5] = (uintptr_t)cube->nz;
+  key.v[6] = (uintptr_t)nbins;
+  key.v[7] = (uintptr_t)d_out;
+  key.v[8] = (uintptr_t)d_counts;
+  key.v[9] = (uintptr_t)d_outliers;
+  key.v[10] = (uintptr_t)d_ws;
+  key.v[11] = (uintptr_t)ws_bytes;
+  key.v[12] = (uintptr_t)dev;
+  if (region) {
+    key.v[13] = 1;
+    key.v[14] = (uintptr_t)region->x0;
+    key.v[15] = (uintptr_t)region->y0;
+    key.v[16] = (uintptr_t)region->z0;
+    key.v[17] = (uintptr_t)region->x1;
+    key.v[18] = (uintptr_t)region->y1;
+    key.v[19] = (uintptr_t)region->z1;
+  }
+  StatsCall c{cube, region, nbins, d_out, d_counts, d_outliers, d_ws, ws_bytes};
+  return graph_run(key, (hipStream_t)stream, enqueue_stats_call, &c);
+}
+
+static int enqueue_stats(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa_result* d_out,
+                         uint64_t* d_counts, uint64_t* d_outliers, void* d_ws, size_t ws_bytes, tsa_stream_t stream) {
   if (!d_out || !d_counts) return TSA_EINVAL;
   if (nbins < 1 || nbins > 65536) return TSA_EINVAL;
   Prep P;

@@ -279,3 +279,48 @@ def test_stats_many_bins_outside_window(case):
     check_moments(res, want, dt, case)
     check_median(res["median"], want["median"], dt, case)
     check_hist(c, o, want["counts"], want["outliers"], case)
+
+
+def test_stats_graph_replays_match_direct_launch():
+    """tsa_stats captures its launches into a graph the second time an
+    argument set comes and replays it afterwards.  Every replay, with eager
+    GPU work and synchronisation between them, must equal the directly
+    launched call (tracing makes a call launch directly), for the whole cube
+    and for a box; the direct results match the oracle."""
+    import ctypes
+    spec = synth.scaled(synth.SPECS["c1"], 96, 96, 64)
+    host, _ = synth.generate(spec)
+    dev = _dev(host)
+    nbins = 256
+    api = tsa.capi()
+    lib = api.lib
+    lib.tsa_trace_enable.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    c = tsa.cube_of(dev)
+    out = torch.empty(72, dtype=torch.uint8, device="cuda:0")
+    counts = torch.empty(nbins, dtype=torch.int64, device="cuda:0")
+    outl = torch.empty(2, dtype=torch.int64, device="cuda:0")
+    for box in (None, (5, 7, 3, 90, 81, 60)):
+        _say("case stats graph replays", box)
+        reg = tsa.region_of(box)
+        ws = tsa.workspace(tsa.OP_STATS, dev, box, nbins)
+
+        def call():
+            st = api.tsa_stats(ctypes.byref(c), tsa._rp(reg), nbins, out.data_ptr(), counts.data_ptr(),
+                               outl.data_ptr(), ws.data_ptr(), ws.numel(), torch.cuda.current_stream().cuda_stream)
+            assert st == 0
+            torch.cuda.synchronize()
+            return out.cpu().numpy().tobytes(), counts.cpu().numpy().tobytes(), outl.cpu().numpy().tobytes()
+
+        assert lib.tsa_trace_enable(1, 64) == 0
+        direct = call()
+        assert lib.tsa_trace_enable(0, 0) == 0
+        r = {k: tsa.results_to_numpy(out)[0][k].item() for k in tsa.results_to_numpy(out).dtype.names}
+        want = oracle.stats(host, nbins, box)
+        check_moments(r, want, "f32", f"direct {box}")
+        check_median(r["median"], want["median"], "f32", f"direct {box}")
+        for rep in range(5):
+            x = (dev * 2.0).sum()  # eager GPU work between replays
+            torch.cuda.synchronize()
+            del x
+            got = call()  # 1st: direct launch, 2nd: capture, then replays
+            assert got == direct, (box, rep)
