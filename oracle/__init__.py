@@ -31,13 +31,25 @@ slow restatement of what the paper (arXiv 1211.4896) defines:
 * spectrum     -- Section 4.4's 3-D spectrum tool: the cube sampled along
                   arbitrary rays at a constant step, each sample a trilinear
                   interpolation of its eight neighbouring voxels (Fig. 8).
+* stats_exact, stats_boxes, stats_streaming
+               -- the same trio as ``stats`` for inputs too large to sort or
+                  to hold in memory (tsa_oracle_stream.c): exact sums of the
+                  values and of their squares (one rounding of the mean and of
+                  M2 at the end), the histogram with the same bin formula, and
+                  the lower median by counting keys on their top 16 bits, then
+                  on their low 16 bits inside the bucket holding the rank.
+                  ``stats_streaming`` regenerates a synthetic cube slab by slab
+                  (the 206 GB cube), ``stats_boxes`` takes a batch of boxes.
+                  Host threads split the values; they merge by integer
+                  addition, so the results do not depend on the thread count.
 
 NaN is the NULL value and is excluded everywhere.  The C parts live in
-tsa_oracle.c and are built with gcc by ``build()``.
+tsa_oracle.c and tsa_oracle_stream.c and are built with gcc by ``build()``.
 """
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -45,6 +57,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "tsa_oracle.c")
+_SRC_STREAM = os.path.join(_HERE, "tsa_oracle_stream.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -57,12 +70,33 @@ class _Moments(ctypes.Structure):
                 ("max", ctypes.c_double)]
 
 
+class _Acc1(ctypes.Structure):  # oracle_acc1 (tsa_oracle_stream.c)
+    _fields_ = [("n", ctypes.c_uint64), ("nan", ctypes.c_uint64), ("pinf", ctypes.c_uint64),
+                ("minf", ctypes.c_uint64), ("kmin", ctypes.c_uint32), ("kmax", ctypes.c_uint32),
+                ("s", ctypes.c_int64 * 256), ("qh", ctypes.c_uint64 * 256), ("ql", ctypes.c_uint64 * 256),
+                ("top", ctypes.c_uint64 * 65536)]
+
+
+class _Pass2(ctypes.Structure):  # oracle_pass2_args
+    _fields_ = [("lo", ctypes.c_float), ("hi", ctypes.c_float), ("scale", ctypes.c_float), ("nbins", ctypes.c_int32),
+                ("hist_on", ctypes.c_int32), ("sel", ctypes.c_uint32), ("sel_on", ctypes.c_int32)]
+
+
+class _Acc2(ctypes.Structure):  # oracle_acc2
+    _fields_ = [("below", ctypes.c_uint64), ("above", ctypes.c_uint64), ("low", ctypes.c_uint64 * 65536)]
+
+
+BOX_OUT_DTYPE = np.dtype([("n", "<u8"), ("nan", "<u8"), ("pinf", "<u8"), ("minf", "<u8"), ("kmin", "<u4"),
+                          ("kmax", "<u4"), ("median_key", "<u4"), ("hist_on", "<i4"), ("status", "<i4"),
+                          ("pad", "<i4")])
+
+
 def build(force: bool = True) -> str:
     """Compile liboracle.so (gcc, no fast-math, no FP contraction)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-                               "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-pthread",
+                               "-o", tmp, _SRC, _SRC_STREAM, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -90,6 +124,26 @@ def _load():
         lib.oracle_median_sort.argtypes = [P, ctypes.c_int, I64, I64, I64, P, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_uint64)]
         lib.oracle_median_sort.restype = ctypes.c_int
+        lib.oracle_acc1_size.restype = ctypes.c_size_t
+        lib.oracle_acc2_size.restype = ctypes.c_size_t
+        assert lib.oracle_acc1_size() == ctypes.sizeof(_Acc1) and lib.oracle_acc2_size() == ctypes.sizeof(_Acc2)
+        lib.oracle_acc1_init.argtypes = [ctypes.POINTER(_Acc1)]
+        lib.oracle_acc1_init.restype = None
+        lib.oracle_acc1_box.argtypes = [P, ctypes.c_int, I64, I64, I64, P, ctypes.POINTER(_Acc1)]
+        lib.oracle_acc1_box.restype = ctypes.c_int
+        lib.oracle_acc2_box.argtypes = [P, ctypes.c_int, I64, I64, I64, P, ctypes.POINTER(_Pass2), ctypes.POINTER(_Acc2),
+                                        P]
+        lib.oracle_acc2_box.restype = ctypes.c_int
+        lib.oracle_pass1_array.argtypes = [P, ctypes.c_int, I64, ctypes.c_int, ctypes.POINTER(_Acc1)]
+        lib.oracle_pass1_array.restype = ctypes.c_int
+        lib.oracle_pass2_array.argtypes = [P, ctypes.c_int, I64, ctypes.c_int, ctypes.POINTER(_Pass2),
+                                           ctypes.POINTER(_Acc2), P]
+        lib.oracle_pass2_array.restype = ctypes.c_int
+        lib.oracle_rank_bin.argtypes = [P, I64, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]
+        lib.oracle_rank_bin.restype = I64
+        lib.oracle_boxes.argtypes = [P, ctypes.c_int, I64, I64, I64, P, I64, ctypes.c_int32, ctypes.c_int, P, P, P, P,
+                                     P]
+        lib.oracle_boxes.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -278,7 +332,9 @@ def mad(a: np.ndarray, region=None):
     m is the lower median; deviations |x - m| are rounded to single precision
     for float32 cubes (numpy float32 arithmetic: one IEEE subtraction, then an
     exact absolute value) and exact integers for int16 cubes; the MAD is their
-    lower median."""
+    lower median over all n valid values.  A value equal to m deviates by +0,
+    written out so that it also holds when m is infinite (the IEEE difference
+    inf - inf would be NaN)."""
     vals = _valid_values(a, region)
     n = vals.size
     if n == 0:
@@ -286,7 +342,11 @@ def mad(a: np.ndarray, region=None):
     k = (n - 1) // 2
     m = _select(vals, k)
     if vals.dtype == np.float32:
-        d = np.abs(vals - np.float32(m))
+        m32 = np.float32(m)
+        with np.errstate(invalid="ignore"):
+            diff = np.abs(vals - m32)
+        d = np.where(vals == m32, np.float32(0.0), diff).astype(np.float32)
+        assert not np.isnan(d).any()
     else:
         d = np.abs(vals.astype(np.int32) - np.int32(m))
     return float(m), float(np.partition(d, k)[k]), n
@@ -379,4 +439,218 @@ def spectrum(a: np.ndarray, origins, steps, nsamples: int) -> np.ndarray:
             used = w != 0.0
             acc[used] = acc[used] + w[used] * v[used]
         out[r, inside] = acc
+    return out
+
+
+# ---------------------------------------------------------------------------
+# large inputs: exact sums, two-level key counts (tsa_oracle_stream.c)
+# ---------------------------------------------------------------------------
+
+def _threads(threads=None) -> int:
+    if threads:
+        return int(threads)
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def value_of_key(k: int) -> float:
+    """The float32 value of an order key (the inverse of the key map)."""
+    k = int(k) & 0xFFFFFFFF
+    u = (k & 0x7FFFFFFF) if (k & 0x80000000) else (~k & 0xFFFFFFFF)
+    return float(np.array([u], dtype=np.uint32).view(np.float32)[0])
+
+
+def exact_moments(n, nan, pinf, minf, kmin, kmax, s, qh, ql) -> dict:
+    """Moments from exact per-exponent bins: the value with biased float32
+    exponent E (E = 1 for denormals) and signed significand M is M * 2^(E-150),
+    so S = sum of s[E] * 2^(E-1) and Q = sum of (qh[E] * 2^24 + ql[E]) * 2^(2E-2)
+    are the exact sum and sum of squares in units of 2^-149 and 2^-298.  Then
+    mean = S / n and M2 = (n Q - S^2) / n are each rounded once (Python's
+    integer division is correctly rounded); std = sqrt(M2 / n) with M2 / n
+    rounded once.  Infinities, one repeated value and n = 0 as in moments()."""
+    n, nan = int(n), int(nan)
+    out = {"count": n, "nan_count": nan}
+    qn = float("nan")
+    if n == 0:
+        out.update(mean=qn, m2=qn, std=qn, min=qn, max=qn)
+        return out
+    out["min"], out["max"] = value_of_key(kmin), value_of_key(kmax)
+    if int(kmin) == int(kmax):
+        out.update(mean=out["min"], m2=0.0, std=0.0)
+        return out
+    if pinf or minf:
+        mean = qn if (pinf and minf) else (math.inf if pinf else -math.inf)
+        out.update(mean=mean, m2=qn, std=qn)
+        return out
+    s = np.asarray(s, dtype=np.int64)
+    qh = np.asarray(qh, dtype=np.uint64)
+    ql = np.asarray(ql, dtype=np.uint64)
+    S = 0
+    for e in np.nonzero(s)[0]:
+        S += int(s[e]) << (int(e) - 1)
+    Q = 0
+    for e in np.nonzero(qh | ql)[0]:
+        Q += ((int(qh[e]) << 24) + int(ql[e])) << (2 * int(e) - 2)
+    num = n * Q - S * S  # n^2 * 2^298 * var, exact
+    assert num >= 0
+    out["mean"] = S / (n << 149)
+    out["m2"] = num / (n << 298)
+    out["std"] = math.sqrt(num / ((n * n) << 298))
+    return out
+
+
+def _acc1_moments(a: "_Acc1") -> dict:
+    return exact_moments(a.n, a.nan, a.pinf, a.minf, a.kmin, a.kmax, np.ctypeslib.as_array(a.s),
+                         np.ctypeslib.as_array(a.qh), np.ctypeslib.as_array(a.ql))
+
+
+def _pass2_args(mo: dict, nbins: int, a1: "_Acc1"):
+    """Histogram range (the values' own [min, max]) and the median's top-16 bucket."""
+    lib = _load()
+    p = _Pass2()
+    p.nbins = nbins
+    p.hist_on = 0
+    if mo["count"] > 0:
+        lo, hi = np.float32(mo["min"]), np.float32(mo["max"])
+        sc = ctypes.c_float()
+        if lib.oracle_hist_scale(float(lo), float(hi), nbins, ctypes.byref(sc)) == 0:
+            p.lo, p.hi, p.scale, p.hist_on = float(lo), float(hi), sc.value, 1
+        k = (mo["count"] - 1) // 2
+        cum = ctypes.c_uint64()
+        top = lib.oracle_rank_bin(ctypes.addressof(a1.top), 65536, k, ctypes.byref(cum))
+        assert top >= 0
+        p.sel, p.sel_on = top, 1
+        return p, k - cum.value
+    return p, 0
+
+
+def _finish(mo: dict, p: "_Pass2", k_low: int, a2: "_Acc2", counts: np.ndarray) -> dict:
+    lib = _load()
+    out = dict(mo)
+    nb = len(counts)
+    if p.hist_on:
+        out["counts"] = counts
+        out["outliers"] = np.array([a2.below, a2.above], dtype=np.uint64)
+        out["hist_skipped"] = False
+    else:
+        out["counts"] = np.zeros(nb, dtype=np.uint64)
+        out["outliers"] = np.zeros(2, dtype=np.uint64)
+        out["hist_skipped"] = True
+    if mo["count"] == 0:
+        out["median"] = float("nan")
+    else:
+        cum = ctypes.c_uint64()
+        low = lib.oracle_rank_bin(ctypes.addressof(a2.low), 65536, k_low, ctypes.byref(cum))
+        assert low >= 0
+        out["median"] = value_of_key((p.sel << 16) | low)
+    return out
+
+
+def stats_exact(a: np.ndarray, nbins: int, region=None, threads=None) -> dict:
+    """``stats`` of one array or region by the large-input method (threaded
+    over the values when region is None).  Same keys as ``stats``."""
+    lib = _load()
+    a, dt, nx, ny, nz = _cube(a)
+    b, bp = _box(region)
+    T = _threads(threads)
+    a1 = _Acc1()
+    lib.oracle_acc1_init(ctypes.byref(a1))
+    if bp is None:
+        if lib.oracle_pass1_array(a.ctypes.data, dt, a.size, T, ctypes.byref(a1)) != 0:
+            raise ValueError("bad arguments")
+    elif lib.oracle_acc1_box(a.ctypes.data, dt, nx, ny, nz, bp, ctypes.byref(a1)) != 0:
+        raise ValueError("invalid region or dtype")
+    mo = _acc1_moments(a1)
+    p, k_low = _pass2_args(mo, nbins, a1)
+    a2 = _Acc2()
+    counts = np.zeros(nbins, dtype=np.uint64)
+    if mo["count"] > 0:
+        if bp is None:
+            lib.oracle_pass2_array(a.ctypes.data, dt, a.size, T, ctypes.byref(p), ctypes.byref(a2), counts.ctypes.data)
+        else:
+            lib.oracle_acc2_box(a.ctypes.data, dt, nx, ny, nz, bp, ctypes.byref(p), ctypes.byref(a2),
+                                counts.ctypes.data)
+    return _finish(mo, p, k_low, a2, counts)
+
+
+def stats_boxes(a: np.ndarray, boxes, nbins: int, threads=None, chunk: int = 8192):
+    """``stats`` of every box of a batch (boxes int64[nq, 6], half-open), boxes
+    spread over host threads.  Returns (list of dicts without the histogram,
+    counts uint64[nq, nbins]); a bad box has status -1 in its dict."""
+    lib = _load()
+    a, dt, nx, ny, nz = _cube(a)
+    boxes = np.ascontiguousarray(np.asarray(boxes, dtype=np.int64).reshape(-1, 6))
+    nq = len(boxes)
+    T = _threads(threads)
+    counts = np.zeros((nq, nbins), dtype=np.uint64)
+    res = []
+    for q0 in range(0, nq, chunk):
+        q1 = min(nq, q0 + chunk)
+        m = q1 - q0
+        out = np.zeros(m, dtype=BOX_OUT_DTYPE)
+        s = np.zeros((m, 256), dtype=np.int64)
+        qh = np.zeros((m, 256), dtype=np.uint64)
+        ql = np.zeros((m, 256), dtype=np.uint64)
+        cview = counts[q0:q1]
+        if lib.oracle_boxes(a.ctypes.data, dt, nx, ny, nz, boxes[q0:q1].ctypes.data, m, nbins, T, out.ctypes.data,
+                            s.ctypes.data, qh.ctypes.data, ql.ctypes.data, cview.ctypes.data) != 0:
+            raise ValueError("bad arguments")
+        for i in range(m):
+            o = out[i]
+            if o["status"] != 0:
+                res.append({"status": int(o["status"])})
+                continue
+            d = exact_moments(o["n"], o["nan"], o["pinf"], o["minf"], o["kmin"], o["kmax"], s[i], qh[i], ql[i])
+            d["status"] = 0
+            d["hist_skipped"] = not bool(o["hist_on"])
+            d["median"] = value_of_key(o["median_key"]) if o["n"] > 0 else float("nan")
+            res.append(d)
+    return res, counts
+
+
+def stats_streaming(spec, nbins: int, threads=None, slab_voxels: int = 1 << 28, on_slab=None, log=None) -> dict:
+    """``stats`` of a whole synthetic cube (synth.CubeSpec) that need not fit
+    in memory: pass 1 regenerates it in z-slabs of about slab_voxels voxels
+    and counts, pass 2 regenerates it again for the histogram and the
+    median's low key bits.  on_slab(z0, z1, array) sees every slab of pass 1
+    (the same bytes the generator gives any caller); log(str) reports
+    progress.  Also returns the generator's NaN count as "generator_nan"."""
+    import synth
+
+    lib = _load()
+    T = _threads(threads)
+    dt = F32 if spec.dtype == "f32" else I16
+    planes = max(1, slab_voxels // (spec.nx * spec.ny))
+    a1 = _Acc1()
+    lib.oracle_acc1_init(ctypes.byref(a1))
+    gen_nan = 0
+    slabs = list(range(0, spec.nz, planes))
+    for i, z0 in enumerate(slabs):
+        z1 = min(spec.nz, z0 + planes)
+        arr, nn = synth.generate(spec, z0, z1, threads=T)
+        gen_nan += nn
+        if on_slab is not None:
+            on_slab(z0, z1, arr)
+        lib.oracle_pass1_array(arr.ctypes.data, dt, arr.size, T, ctypes.byref(a1))
+        if log and (i % 8 == 7 or i == len(slabs) - 1):
+            log(f"oracle pass 1: slab {i + 1}/{len(slabs)}")
+        del arr
+    mo = _acc1_moments(a1)
+    p, k_low = _pass2_args(mo, nbins, a1)
+    a2 = _Acc2()
+    counts = np.zeros(nbins, dtype=np.uint64)
+    if mo["count"] > 0:
+        for i, z0 in enumerate(slabs):
+            z1 = min(spec.nz, z0 + planes)
+            arr, _ = synth.generate(spec, z0, z1, threads=T)
+            lib.oracle_pass2_array(arr.ctypes.data, dt, arr.size, T, ctypes.byref(p), ctypes.byref(a2),
+                                   counts.ctypes.data)
+            if log and (i % 8 == 7 or i == len(slabs) - 1):
+                log(f"oracle pass 2: slab {i + 1}/{len(slabs)}")
+            del arr
+    out = _finish(mo, p, k_low, a2, counts)
+    out["generator_nan"] = gen_nan
     return out

@@ -82,13 +82,17 @@ static void nsum_add(double* s, double* c, double x) {
  * M2 = sum (x-m)^2 - (sum (x-m))^2 / n with m the pass-1 mean, which is the
  * same quantity as sum x^2 - (sum x)^2 / n without its cancellation.
  * min/max (Section 4.1: known at load time) are taken in the same pass.
+ * Infinities: the sum of values holding +inf is +inf, holding -inf is -inf,
+ * holding both is undefined, so the mean is +inf, -inf or NaN and the spread
+ * is undefined (NaN).  A region whose valid values are all the same value
+ * (an infinity included) has mean = that value and M2 = std = 0.
  * Returns 0, or -1 for an invalid region or dtype.
  */
 int oracle_moments(const void* data, int dtype, int64_t nx, int64_t ny, int64_t nz,
                    const int64_t* box, oracle_moments_t* out) {
   obox B;
   if ((dtype != OR_F32 && dtype != OR_I16) || !box_ok(nx, ny, nz, box, &B)) return -1;
-  uint64_t n = 0, nn = 0;
+  uint64_t n = 0, nn = 0, npinf = 0, nminf = 0;
   double s = 0.0, c = 0.0, mn = NAN, mx = NAN;
   for (int64_t z = B.z0; z < B.z1; ++z)
     for (int64_t y = B.y0; y < B.y1; ++y)
@@ -106,6 +110,10 @@ int oracle_moments(const void* data, int dtype, int64_t nx, int64_t ny, int64_t 
           if (tot_less(mx, v)) mx = v;
         }
         ++n;
+        if (isinf(v)) {
+          if (v > 0) ++npinf; else ++nminf;
+          continue;
+        }
         nsum_add(&s, &c, v);
       }
   out->count = n;
@@ -114,6 +122,16 @@ int oracle_moments(const void* data, int dtype, int64_t nx, int64_t ny, int64_t 
   out->max = mx;
   if (n == 0) {
     out->mean = out->m2 = out->std = NAN;
+    return 0;
+  }
+  if (!tot_less(mn, mx)) { /* every valid value is the same value */
+    out->mean = mn;
+    out->m2 = out->std = 0.0;
+    return 0;
+  }
+  if (npinf || nminf) {
+    out->mean = (npinf && nminf) ? NAN : (npinf ? INFINITY : -INFINITY);
+    out->m2 = out->std = NAN;
     return 0;
   }
   double mean = (s + c) / (double)n;

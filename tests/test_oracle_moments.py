@@ -145,3 +145,23 @@ def test_mistakes_are_caught():
     assert m["std"] == pytest.approx(math.sqrt(99 / 12), rel=1e-15)
     assert m["std"] != pytest.approx(math.sqrt(99 / 12 * 10 / 9), rel=1e-6)
     assert m["m2"] == pytest.approx(82.5, rel=1e-15)
+
+
+def test_moments_with_infinities():
+    """The sum of values holding +inf is +inf (-inf: -inf, both: undefined), so
+    the mean is +inf, -inf or NaN and the spread undefined; a set holding one
+    value only has that value as its mean and no spread."""
+    def mo(v):
+        return oracle.moments(np.array(v, dtype=np.float32))
+    r = mo([1.0, 2.0, np.inf, np.nan])
+    assert r["mean"] == math.inf and math.isnan(r["std"]) and math.isnan(r["m2"]) and r["count"] == 3
+    r = mo([-np.inf, 1.0, -np.inf])
+    assert r["mean"] == -math.inf and math.isnan(r["std"])
+    r = mo([np.inf, -np.inf, 3.0])
+    assert math.isnan(r["mean"]) and math.isnan(r["std"])
+    r = mo([np.inf, np.inf, np.nan])
+    assert r["mean"] == math.inf and r["std"] == 0.0 and r["m2"] == 0.0 and r["count"] == 2
+    r = mo([-0.0, 0.0])  # two values under totalOrder, no spread either way
+    assert r["mean"] == 0.0 and r["std"] == 0.0 and r["min"] == 0.0 and math.copysign(1, r["min"]) < 0
+    r = mo([0.1] * 7)
+    assert r["mean"] == float(np.float32(0.1)) and r["std"] == 0.0

@@ -99,3 +99,34 @@ def test_mad_exhaustive_small():
             m = s[(n - 1) // 2]
             d = sorted(abs(v - m) for v in s)  # exact here: values on a 2^-1 grid
             assert oracle.mad(x)[1] == d[(n - 1) // 2]
+
+
+def test_mad_infinite_median():
+    """A value equal to the median deviates by zero, also when the median is
+    infinite (the IEEE difference inf - inf would be NaN); the rank is taken
+    over all valid values."""
+    # sorted 1, inf, inf, inf: lower median (rank 1) = inf; deviations inf, 0, 0, 0 -> rank 1 = 0
+    assert oracle.mad(np.float32([np.inf, np.inf, np.inf, 1]))[:3] == (math.inf, 0.0, 4)
+    # sorted -inf, -inf, 0: median -inf; deviations 0, 0, inf -> 0
+    assert oracle.mad(np.float32([-np.inf, -np.inf, 0]))[:3] == (-math.inf, 0.0, 3)
+    # median inf with a minority at inf: deviations inf (finite values) and 0 (the infinities)
+    m, mad, n = oracle.mad(np.float32([1, 2, np.inf, np.inf, np.inf, np.nan]))
+    assert (m, mad, n) == (math.inf, 0.0, 5)
+    # median finite, infinities present: their deviation is inf
+    m, mad, n = oracle.mad(np.float32([1, 2, 3, np.inf, -np.inf]))
+    assert (m, mad, n) == (2.0, 1.0, 5)  # deviations 1, 0, 1, inf, inf -> sorted 0 1 1 inf inf -> rank 2 = 1
+    m, mad, n = oracle.mad(np.float32([1, np.inf, np.inf, -np.inf, -np.inf]))
+    assert (m, mad, n) == (1.0, math.inf, 5)
+
+
+def test_mad_brute_force_with_infinities():
+    """Brute force by the definition on multisets drawn from values that
+    include both infinities and signed zeros."""
+    pool = np.float32([-np.inf, -1.0, -0.0, 0.0, 2.0, np.inf])
+    for n in range(1, 6):
+        for combo in itertools.product(range(len(pool)), repeat=n):
+            x = pool[list(combo)]
+            s = sorted((float(v) for v in x), key=_tot_key)
+            m = s[(n - 1) // 2]
+            d = sorted(0.0 if v == m else abs(v - m) for v in s)
+            assert oracle.mad(x)[:2] == (m, d[(n - 1) // 2]), x
