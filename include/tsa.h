@@ -184,7 +184,9 @@ int tsa_quantile(const tsa_cube* cube, const tsa_region* region, double q, int32
 /*
  * Median absolute deviation (Section 4.3 names it as an extension of the
  * median method): m = the lower median, then the lower median of |x - m| over
- * the non-NaN values, x - m rounded to single precision (int16: exact).
+ * the non-NaN values, x - m rounded to single precision (int16: exact).  A
+ * value equal to m deviates by +0, also when m is infinite (where the IEEE
+ * difference would be NaN), so the rank is taken over all count values.
  * Four radix passes over the data.  d_out (device, 3 doubles) = (m, MAD,
  * count); NaN, NaN, 0 without a valid voxel.
  */

@@ -53,6 +53,17 @@ int tsa_internal_read_probe(const void* src, size_t bytes, uint32_t* d_sink, tsa
 /* Number of sink words tsa_internal_read_probe writes on the current device. */
 int32_t tsa_internal_probe_blocks(void);
 
+/*
+ * Testing support: caps every bounded wait of the region batch's persistent
+ * kernel at `polls` polls (polls < 0: the default cap).  With 0 polls every
+ * wait gives up at once, so a test drives the give-up path -- the waiting
+ * block stops, the boxes left unfinished report TSA_EDEVICE -- while every
+ * kernel still exits.  Batches launched while a cap is set bypass the launch
+ * graph cache.  Process-wide; not meant to be changed while other threads
+ * launch batches.  Returns TSA_OK.
+ */
+int tsa_internal_batch_wait_limit(int32_t polls);
+
 #ifdef __cplusplus
 }
 #endif

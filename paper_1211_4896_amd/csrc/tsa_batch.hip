@@ -19,6 +19,7 @@
 // boxes left unfinished report TSA_EDEVICE.
 #include <math.h>
 
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -66,6 +67,7 @@ struct BArgs {
   int32_t nq, nbins;
   uint32_t rshift, tile_units, max_tiles, cand_max, pool_keys;  // tile_units 0: chosen on the device
   uint32_t grid;  // persistent blocks
+  uint32_t spin_limit;  // polls per wait, at most
   int32_t vec;
   tsa_result* results;
   uint64_t* hists;
@@ -255,12 +257,13 @@ TSA_DEV EpScratch ep_scratch(uint32_t* lds) {
 }
 constexpr size_t kEpLdsBytes = (size_t)kEpOffWords * 4 + (3 * 8 + 2 * 4) * (size_t)kBBlock;
 
-// Thread 0 waits until *p >= v (bounded); result broadcast to the block.
-TSA_DEV bool block_wait_ge(const uint32_t* p, uint32_t v, uint32_t* err, BShared& sh) {
+// Thread 0 waits until *p >= v (bounded by `limit` polls and kWaitTicks);
+// result broadcast to the block.
+TSA_DEV bool block_wait_ge(const uint32_t* p, uint32_t v, uint32_t* err, BShared& sh, uint32_t limit) {
   if (threadIdx.x == 0) {
     uint32_t ok = 0;
     const uint64_t t0 = wall_clock64();
-    for (uint32_t it = 0; it < kSpinLimit; ++it) {
+    for (uint32_t it = 0; it < limit; ++it) {
       // relaxed polls, one acquire once the value is there (an agent-scope
       // acquire invalidates this XCD's L2)
       if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= v) {
@@ -315,8 +318,8 @@ TSA_DEV void epilogue1(const BArgs& a, uint32_t q, BShared& sh, uint32_t* lds) {
   for (uint32_t i = t; i < g.ntiles; i += bs) {
     const Partial p = a.parts1[tb + i];
     double pn, pm, pq;
-    partial_stats_b(p, DT, pn, pm, pq);
-    chan_merge_b(n, m, m2, pn, pm, pq);
+    partial_stats(p, DT, pn, pm, pq);
+    chan_merge(n, m, m2, pn, pm, pq);
     if (p.n) {
       mn = min(mn, p.kmin);
       mx = max(mx, p.kmax);
@@ -331,7 +334,7 @@ TSA_DEV void epilogue1(const BArgs& a, uint32_t q, BShared& sh, uint32_t* lds) {
   for (int s2 = bs / 2; s2 > 0; s2 >>= 1) {
     if (t < s2) {
       double x = ep.mn[t], y = ep.mm[t], z = ep.mq[t];
-      chan_merge_b(x, y, z, ep.mn[t + s2], ep.mm[t + s2], ep.mq[t + s2]);
+      chan_merge(x, y, z, ep.mn[t + s2], ep.mm[t + s2], ep.mq[t + s2]);
       ep.mn[t] = x;
       ep.mm[t] = y;
       ep.mq[t] = z;
@@ -406,12 +409,21 @@ TSA_DEV void epilogue1(const BArgs& a, uint32_t q, BShared& sh, uint32_t* lds) {
         s.var_on = (DT == 0 && isfinite(mean) && one_pass_m2_at_risk(mean, R.m2 / (double)cnt)) ? 1u : 0u;
         s.shift = s.var_on ? (float)mean : 0.0f;
         s.compact = 0;
-        if (bucket <= a.cand_max) {
-          const uint32_t base = atomicAdd(&a.hdr->pool_top, (uint32_t)bucket);
-          if ((uint64_t)base + bucket <= a.pool_keys) {
-            s.compact = 1;
-            s.cand_base = base;
-            s.cand_n = (uint32_t)bucket;
+        // int16 keys are complete after the second digit: no candidates needed.
+        // The pool counter only advances while the reservation fits (pool_keys
+        // <= 2^28 and a bucket <= cand_max < 2^31, so the sum never wraps): a
+        // box that finds the pool full takes the third pass instead.
+        if (DT == 0 && bucket <= a.cand_max) {
+          uint32_t cur = __hip_atomic_load(&a.hdr->pool_top, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          while ((uint64_t)cur + bucket <= a.pool_keys) {
+            const uint32_t seen = atomicCAS(&a.hdr->pool_top, cur, cur + (uint32_t)bucket);
+            if (seen == cur) {
+              s.compact = 1;
+              s.cand_base = cur;
+              s.cand_n = (uint32_t)bucket;
+              break;
+            }
+            cur = seen;
           }
         }
       }
@@ -621,7 +633,7 @@ __global__ __launch_bounds__(kBBlock) void k_batch(BArgs a) {
         if (c) atomicAdd(dig + b, c);
       }
     } else if (phase == 2) {
-      if (!block_wait_ge(&s.p1_ready, 1u, &a.hdr->err, sh)) return;
+      if (!block_wait_ge(&s.p1_ready, 1u, &a.hdr->err, sh, a.spin_limit)) return;
       if (!s.skip2) {
         const uint32_t hsize = ((uint32_t)a.nbins << a.rshift) + kTrash;
         uint32_t* l2 = lds + hsize;
@@ -656,13 +668,13 @@ __global__ __launch_bounds__(kBBlock) void k_batch(BArgs a) {
       }
     } else {
       // only a box left without a candidate copy can need the last digit
-      if (!block_wait_ge(&s.p1_ready, 1u, &a.hdr->err, sh)) return;
+      if (!block_wait_ge(&s.p1_ready, 1u, &a.hdr->err, sh, a.spin_limit)) return;
       if (t == 0) sh.flag = (DT == 0 && s.skip2 == 0 && s.compact == 0) ? 1u : 0u;
       __syncthreads();
       const bool may3 = sh.flag != 0;
       __syncthreads();
       if (!may3) continue;
-      if (!block_wait_ge(&s.p2_ready, 1u, &a.hdr->err, sh)) return;
+      if (!block_wait_ge(&s.p2_ready, 1u, &a.hdr->err, sh, a.spin_limit)) return;
       if (t == 0) sh.flag = s.need3;
       __syncthreads();
       const bool need3 = sh.flag != 0;
@@ -794,6 +806,10 @@ GraphCache& graphs() {
 bool same_key(const GraphKey& a, const GraphKey& b) { return memcmp(a.v, b.v, sizeof(a.v)) == 0; }
 }  // namespace
 
+// Polls per bounded wait when set (>= 0) by tsa_internal_batch_wait_limit;
+// -1: kSpinLimit.  Calls made while it is set launch directly (no graph).
+static std::atomic<int64_t> g_wait_polls{-1};
+
 bool graphs_enabled() {
   static const bool on = [] {
     const char* e = getenv("TSA_GRAPH");
@@ -879,7 +895,7 @@ int run_region_batch(const tsa_cube* cube, const tsa_region* d_regions, int32_t 
   hipStream_t s = (hipStream_t)stream;
   tsa_tune tuned;
   if (!tune && tune_lookup(cube, nbins, nq, &tuned)) tune = &tuned;
-  if (!graphs_enabled() || trace_active())
+  if (!graphs_enabled() || trace_active() || g_wait_polls.load() >= 0)
     return enqueue_region_batch(cube, d_regions, nq, nbins, d_results, d_hists, tune, d_ws, ws_bytes, s);
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return TSA_EDEVICE;
@@ -943,6 +959,10 @@ static int enqueue_region_batch(const tsa_cube* cube, const tsa_region* d_region
   a.rshift = nbins <= 1024 ? 2u : nbins <= 2048 ? 1u : 0u;
   a.tile_units = tile_units;
   a.grid = (uint32_t)(dev.cus * bpc);
+  {
+    const int64_t polls = g_wait_polls.load();
+    a.spin_limit = polls >= 0 ? (uint32_t)polls : kSpinLimit;
+  }
   a.max_tiles = L.max_tiles;
   a.cand_max = cand_max;
   a.pool_keys = L.pool_keys;
@@ -1006,3 +1026,8 @@ static void bfill(void* p, size_t words, hipStream_t s) {
 }
 
 }  // namespace tsa
+
+extern "C" int tsa_internal_batch_wait_limit(int32_t polls) {
+  tsa::g_wait_polls.store(polls < 0 ? -1 : (int64_t)polls);
+  return TSA_OK;
+}

@@ -17,12 +17,20 @@ __global__ void k_fill32(uint32_t* __restrict__ p, uint64_t n, uint32_t v) {
 // ---------------------------------------------------------------------------
 // moments pass: one Partial per block
 // ---------------------------------------------------------------------------
+// float32 lanes sum about a shift of their own and the partials hold
+// (n, mean, M2); int16 partials hold exact integer sums.
 template <int DT, bool VEC, bool NT>
 __global__ __launch_bounds__(1024) void k_moments(Geom g, Partial* __restrict__ parts) {
   __shared__ MomShared sm;
-  MomAcc<DT> acc;
-  walk<DT, VEC, kUnroll, NT>(g, acc);
-  block_store_partial(acc, sm, parts + blockIdx.x);
+  if constexpr (DT == 0) {
+    ShiftMomAcc acc;
+    walk<DT, VEC, kUnroll, NT>(g, acc);
+    block_store_centered(acc, sm, parts + blockIdx.x);
+  } else {
+    MomAcc<DT> acc;
+    walk<DT, VEC, kUnroll, NT>(g, acc);
+    block_store_partial(acc, sm, parts + blockIdx.x);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -99,45 +107,8 @@ __global__ __launch_bounds__(1024) void k_level3(Geom g, SelState* __restrict__ 
 // one-block epilogues: moments merge and digit selection
 // ---------------------------------------------------------------------------
 
-// Chan et al. pairwise update of (n, mean, M2).
-TSA_DEV void chan_merge(double& na, double& ma, double& qa, double nb, double mb, double qb) {
-  if (nb == 0.0) return;
-  if (na == 0.0) {
-    na = nb;
-    ma = mb;
-    qa = qb;
-    return;
-  }
-  const double n = na + nb;
-  const double d = mb - ma;
-  ma = ma + d * (nb / n);
-  qa = qa + qb + d * d * (na * nb / n);
-  na = n;
-}
-
 TSA_DEV double value_of_key(uint32_t k, int dtype) {
   return dtype == 0 ? (double)__uint_as_float(f32bits_of_key(k)) : (double)i16_of_key(k);
-}
-
-// (n, mean, M2) of one block partial, in double.
-TSA_DEV void partial_stats(const Partial& p, int dtype, double& n, double& m, double& q) {
-  n = (double)p.n;
-  if (p.n == 0) {
-    m = q = 0.0;
-    return;
-  }
-  if (dtype == 0) {
-    m = p.s / n;
-    q = p.q - p.s * m;
-  } else {
-    // exact n*Q - S^2 in 128-bit integers, then one rounding to double
-    const __int128 num = (__int128)p.qi * (__int128)p.n - (__int128)p.si * (__int128)p.si;
-    const int64_t hi = (int64_t)(num >> 64);
-    const uint64_t lo = (uint64_t)num;
-    const double dnum = (double)hi * 18446744073709551616.0 + (double)lo;
-    m = (double)p.si / n;
-    q = dnum / n;
-  }
 }
 
 struct MergeShared {
@@ -148,15 +119,17 @@ struct MergeShared {
 // Whole block: merge np partials in a fixed order (each thread a strided
 // sequence, then a pairwise tree) and write the moments fields of *out.
 // Returns (in every thread) the global count and min/max keys.
+// centered: the partials hold (mean, M2) (k_moments' float32 lanes).
 TSA_DEV void merge_moments(const Partial* __restrict__ parts, int np, int dtype, uint64_t volume, tsa_result* out,
-                           MergeShared& sm, uint64_t& n_out, uint32_t& kmin_out, uint32_t& kmax_out) {
+                           MergeShared& sm, uint64_t& n_out, uint32_t& kmin_out, uint32_t& kmax_out,
+                           bool centered = false) {
   const int t = threadIdx.x, bs = blockDim.x;
   double n = 0.0, m = 0.0, q = 0.0;
   uint32_t mn = 0xFFFFFFFFu, mx = 0u;
   for (int i = t; i < np; i += bs) {
     const Partial p = parts[i];
     double pn, pm, pq;
-    partial_stats(p, dtype, pn, pm, pq);
+    partial_stats(p, dtype, pn, pm, pq, centered);
     chan_merge(n, m, q, pn, pm, pq);
     if (p.n) {
       mn = min(mn, p.kmin);
@@ -216,7 +189,7 @@ __global__ __launch_bounds__(1024) void k_moments_merge(const Partial* __restric
   __shared__ MergeShared sm;
   uint64_t n;
   uint32_t a, b;
-  merge_moments(parts, np, dtype, volume, out, sm, n, a, b);
+  merge_moments(parts, np, dtype, volume, out, sm, n, a, b, dtype == 0);
 }
 
 struct SelectShared {

@@ -362,7 +362,7 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
   if (t == 0) {
     const Partial p = sh.part;
     double n, mean, m2;
-    partial_stats_b(p, 0, n, mean, m2);
+    partial_stats(p, 0, n, mean, m2);
     R.count = p.n;
     R.nan_count = nvox - p.n;
     R.status = TSA_OK;

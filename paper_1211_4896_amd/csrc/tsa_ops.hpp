@@ -84,6 +84,88 @@ struct MomAcc<1, COUNT> {
   TSA_DEV void chunk() {}
 };
 
+// Chan et al.'s pairwise update of (n, mean, M2) (the O(1) combine of
+// Section 4.2's partial sums).  A partial whose mean is infinite (it holds
+// infinities) makes the merged mean the sum of the two means (+inf, -inf, or
+// NaN when both signs occur) and the spread undefined (NaN).
+TSA_DEV void chan_merge(double& na, double& ma, double& qa, double nb, double mb, double qb) {
+  if (nb == 0.0) return;
+  if (na == 0.0) {
+    na = nb;
+    ma = mb;
+    qa = qb;
+    return;
+  }
+  const double n = na + nb;
+  if (!__builtin_isfinite(ma) || !__builtin_isfinite(mb)) {
+    ma = ma + mb;
+    qa = __builtin_nan("");
+    na = n;
+    return;
+  }
+  const double d = mb - ma;
+  ma = ma + d * (nb / n);
+  qa = qa + qb + d * d * (na * nb / n);
+  na = n;
+}
+
+// (n, mean, M2) of one block partial, in double.  centered: the partial holds
+// (mean, M2) already (tsa_moments' shifted lanes); else float32 partials hold
+// the sums S and Q, int16 partials exact integer sums.
+TSA_DEV void partial_stats(const Partial& p, int dtype, double& n, double& m, double& q, bool centered = false) {
+  n = (double)p.n;
+  if (p.n == 0) {
+    m = q = 0.0;
+    return;
+  }
+  if (dtype == 0) {
+    if (centered) {
+      m = p.s;
+      q = p.q;
+    } else {
+      m = p.s / n;
+      q = p.q - p.s * m;
+    }
+  } else {
+    // exact n*Q - S^2 in 128-bit integers, then one rounding to double
+    const __int128 num = (__int128)p.qi * (__int128)p.n - (__int128)p.si * (__int128)p.si;
+    const int64_t hi = (int64_t)(num >> 64);
+    const uint64_t lo = (uint64_t)num;
+    m = (double)p.si / n;
+    q = ((double)hi * 18446744073709551616.0 + (double)lo) / n;
+  }
+}
+
+// float32, one pass, for the moments alone: every lane subtracts a shift c,
+// its first finite valid value, before summing, and keeps sum (x - c) and
+// sum (x - c)^2 in double.  x - c is exact in double (or within 2^-53 when
+// the exponents lie more than 29 apart), so the lane's
+// M2 = sum (x-c)^2 - (sum (x-c))^2 / n loses only the digits that
+// (mean - c)^2 / var costs, where c is one of the lane's own values, instead
+// of the (mean / std)^2 that unshifted sums of x and x^2 lose.  Infinities
+// seen before the first finite value add +-inf either way (c stays 0 until
+// then), so the shift is the same for every finite value of the lane.
+struct ShiftMomAcc {
+  double c = 0.0, s = 0.0, q = 0.0;
+  uint32_t kmin = 0xFFFFFFFFu, kmax = 0u, cnt = 0u;
+  bool have = false;
+  TSA_DEV void operator()(float x, bool in) {
+    const bool ok = Elt<0>::valid(x, in);
+    const double v = (double)x;
+    const bool take = !have && ok && __builtin_isfinite(x);
+    c = take ? v : c;
+    have = have || take;
+    const double d = ok ? v - c : 0.0;
+    s += d;
+    q = __builtin_fma(d, d, q);
+    const uint32_t k = Elt<0>::key(x);
+    kmin = min(kmin, ok ? k : 0xFFFFFFFFu);
+    kmax = max(kmax, ok ? k : 0u);
+    cnt += ok ? 1u : 0u;
+  }
+  TSA_DEV void chunk() {}
+};
+
 // Reduce a block's lanes (fixed order) and store one Partial.
 struct alignas(16) MomShared {
   double s[16], q[16];
@@ -176,6 +258,53 @@ TSA_DEV void block_store_partial(MomAcc<1, COUNT>& a, MomShared& sm, Partial* ou
   }
 }
 
+// Lanes of ShiftMomAcc: each lane's (n, mean, M2), then Chan merges down a
+// fixed tree (lane i takes lane i + o, o = 32 .. 1), the block's waves in
+// order; the Partial holds (n, mean, M2) ("centered") and the key extremes.
+TSA_DEV void block_store_centered(ShiftMomAcc& a, MomShared& sm, Partial* out) {
+  double n = (double)a.cnt, m = 0.0, m2 = 0.0;
+  if (a.cnt) {
+    const double r = a.s / n;
+    m = a.c + r;
+    m2 = a.q - a.s * r;
+    if (m2 < 0.0) m2 = 0.0;  // rounding below zero; NaN (infinite values) stays
+  }
+  const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    const double nb = __shfl_down(n, o), mb = __shfl_down(m, o), qb = __shfl_down(m2, o);
+    if (lane < o) chan_merge(n, m, m2, nb, mb, qb);
+  }
+  const uint32_t kmin = wave_min_u32(a.kmin), kmax = wave_max_u32(a.kmax);
+  if (lane == 0) {
+    sm.s[w] = m;
+    sm.q[w] = m2;
+    sm.cnt[w] = (uint64_t)n;
+    sm.kmin[w] = kmin;
+    sm.kmax[w] = kmax;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = blockDim.x / kWave;
+    double bn = (double)sm.cnt[0], bm = sm.s[0], bq = sm.q[0];
+    uint32_t mn = sm.kmin[0], mx = sm.kmax[0];
+    for (int i = 1; i < nw; ++i) {
+      chan_merge(bn, bm, bq, (double)sm.cnt[i], sm.s[i], sm.q[i]);
+      mn = min(mn, sm.kmin[i]);
+      mx = max(mx, sm.kmax[i]);
+    }
+    Partial p;
+    p.n = (uint64_t)bn;
+    p.kmin = mn;
+    p.kmax = mx;
+    p.s = bm;
+    p.q = bq;
+    p.si = 0;
+    p.qi = 0;
+    *out = p;
+  }
+}
+
 // ---- second moment about a shift (two-pass form, fused path) ----------------
 // sum (x - c)^2 in double: the difference of two float32 values is formed in
 // double (exact unless their exponents lie more than 29 apart, then within
@@ -215,7 +344,10 @@ TSA_DEV void block_store_var(VarAcc& a, MomShared& sm, Partial* out) {
 // ---- |x - m| as the element (median absolute deviation) ----------------------
 // Feeds an accumulator written for float elements with d = |x - m|: one IEEE
 // single-precision subtraction for float32 cubes, exact for int16 cubes (the
-// integer difference is at most 65535, exact in float).  NaN stays NaN.
+// integer difference is at most 65535, exact in float).  A value equal to m
+// deviates by +0, also when both are the same infinity (where the IEEE
+// difference would be NaN), so every non-NaN voxel has a deviation.  NaN
+// stays NaN.
 template <int DT, class Inner>
 struct AbsDev {
   Inner inner;
@@ -225,7 +357,7 @@ struct AbsDev {
   TSA_DEV void operator()(T raw, bool in) {
     float d;
     if constexpr (DT == 0)
-      d = fabsf((float)raw - mf);
+      d = ((float)raw == mf) ? 0.0f : fabsf((float)raw - mf);
     else
       d = (float)abs((int32_t)raw - mi);
     inner(d, in);
@@ -532,39 +664,6 @@ TSA_DEV bool block_select_small(const uint32_t* hist, int nb, uint32_t k, SH& sh
 
 TSA_DEV double bvalue_of_key(uint32_t k, int dtype) {
   return dtype == 0 ? (double)__uint_as_float(f32bits_of_key(k)) : (double)i16_of_key(k);
-}
-
-TSA_DEV void chan_merge_b(double& na, double& ma, double& qa, double nb, double mb, double qb) {
-  if (nb == 0.0) return;
-  if (na == 0.0) {
-    na = nb;
-    ma = mb;
-    qa = qb;
-    return;
-  }
-  const double n = na + nb;
-  const double d = mb - ma;
-  ma = ma + d * (nb / n);
-  qa = qa + qb + d * d * (na * nb / n);
-  na = n;
-}
-
-TSA_DEV void partial_stats_b(const Partial& p, int dtype, double& n, double& m, double& q) {
-  n = (double)p.n;
-  if (p.n == 0) {
-    m = q = 0.0;
-    return;
-  }
-  if (dtype == 0) {
-    m = p.s / n;
-    q = p.q - p.s * m;
-  } else {
-    const __int128 num = (__int128)p.qi * (__int128)p.n - (__int128)p.si * (__int128)p.si;
-    const int64_t hi = (int64_t)(num >> 64);
-    const uint64_t lo = (uint64_t)num;
-    m = (double)p.si / n;
-    q = ((double)hi * 18446744073709551616.0 + (double)lo) / n;
-  }
 }
 
 // ---- radix digits of the key (Section 4.3 replaced by radix selection) --------

@@ -91,6 +91,7 @@ struct tsa_server {
   FullLane fl;
   size_t region_cost = 0;
   size_t budget_used = 0;
+  std::atomic<size_t> budget_peak{0};
   int admitted = 0;
   std::atomic<bool> stop{false};
   std::thread th;
@@ -215,6 +216,7 @@ bool admit(tsa_server* s) {
       P.pop_front();
       it->cost = c;
       s->budget_used += c;
+      if (s->budget_used > s->budget_peak.load()) s->budget_peak.store(s->budget_used);
       s->admitted++;
       it->resp.t_admit = now_s();
       A.push_back(it);
@@ -520,6 +522,12 @@ static int submit_item(tsa_server* s, const tsa_request* r, int64_t replay_index
     delete it;
     return TSA_EINVAL;
   }
+  // a request costing more than the whole budget could never be admitted and
+  // would hold up every later request of its class
+  if (s->cfg.scratch_bytes && item_cost(s, it) > s->cfg.scratch_bytes) {
+    delete it;
+    return TSA_ENOMEM;
+  }
   if (s->arrivals.size() >= (1u << 20)) {
     delete it;
     return TSA_EBUSY;
@@ -590,16 +598,18 @@ int tsa_server_replay(tsa_server* s, const tsa_request* reqs, const double* t_ar
 int tsa_server_stats(tsa_server* s, char* buf, size_t len) {
   if (!s || !buf) return TSA_EINVAL;
   std::lock_guard<std::mutex> g(s->mu);
-  char tmp[512];
+  char tmp[768];
   const int n = snprintf(tmp, sizeof(tmp),
                          "{\"batches\": %llu, \"batched_requests\": %llu, \"max_batch\": %llu, \"full_requests\": "
                          "%llu, \"full_scans\": %llu, \"admission_waits\": %llu, \"submitted\": %llu, "
-                         "\"finished\": %llu}",
+                         "\"finished\": %llu, \"scratch_bytes\": %llu, \"budget_peak\": %llu, "
+                         "\"region_cost\": %llu}",
                          (unsigned long long)s->n_batches, (unsigned long long)s->n_batch_items,
                          (unsigned long long)s->max_batch_seen, (unsigned long long)s->n_full,
                          (unsigned long long)s->n_scans,
                          (unsigned long long)s->n_admit_waits, (unsigned long long)s->submitted,
-                         (unsigned long long)s->finished);
+                         (unsigned long long)s->finished, (unsigned long long)s->cfg.scratch_bytes,
+                         (unsigned long long)s->budget_peak.load(), (unsigned long long)s->region_cost);
   if (n < 0 || (size_t)n + 1 > len) return TSA_ENOMEM;
   memcpy(buf, tmp, (size_t)n + 1);
   return n;

@@ -43,10 +43,14 @@ def check_moments(got: dict, want: dict, dtype: str = "f32", what: str = ""):
         return
     assert same_value(got["min"], want["min"], dtype), (what, "min", got["min"], want["min"])
     assert same_value(got["max"], want["max"], dtype), (what, "max", got["max"], want["max"])
-    if not (math.isfinite(want["mean"]) and math.isfinite(want["std"])):
-        # infinities in the data: no finite spread exists; unless every value
-        # is the same (std 0 by definition), the kernels report it as NaN too
-        if want["min"] != want["max"] and math.isnan(want["std"]):
+    if not math.isfinite(want["mean"]):
+        # infinities in the data: the mean is +inf, -inf or NaN (both signs)
+        # and, unless every value is the same (std 0), the spread is NaN
+        assert same_value(got["mean"], want["mean"], "f64"), (what, "mean", got["mean"], want["mean"])
+        if want["std"] == 0.0:
+            assert got["std"] == 0.0 and got["m2"] == 0.0, (what, "std", got["std"])
+        else:
+            assert math.isnan(want["std"]), (what, want)
             assert math.isnan(got["std"]) and math.isnan(got["m2"]), (what, "std", got["std"])
         return
     rms = math.hypot(want["mean"], want["std"])

@@ -1,4 +1,5 @@
 """Batched region queries (one persistent kernel) against the CPU oracle, per query."""
+import ctypes
 import math
 import sys
 
@@ -193,3 +194,70 @@ def test_autotuner_choice_is_used_and_correct():
     best, ms = tsa.tune_region_batch(dev, boxes, 64, reps=1)
     assert best[0] in (65536, 262144, 1048576) and best[2] in (2, 4, 6, 8) and ms > 0
     _check_batch(host, dev, boxes, 64, what="tuned")  # tune=None: the remembered choice
+
+
+def test_batch_candidate_pool_fills_without_wrapping():
+    """5000 boxes of 2^20 voxels whose values all fall into one first-digit key
+    bucket ([1, 1.125): one exponent, top three significand bits zero), so each
+    box asks the shared candidate pool for its whole volume: their requests sum
+    past 2^32.  The pool hands out ranges only while they fit; the boxes that
+    find it full take the third pass.  Every box against the oracle."""
+    rng = np.random.default_rng(31)
+    nx, ny, nz = 512, 512, 256
+    top = np.nextafter(np.float32(1.125), np.float32(0.0))
+    host = np.minimum(np.float32(1.0) + rng.random((nz, ny, nx), dtype=np.float32) * np.float32(0.125), top)
+    host = host.astype(np.float32)
+    nq = 5000
+    e = np.array([128, 128, 64])
+    o = np.stack([rng.integers(0, n - k + 1, nq) for n, k in zip((nx, ny, nz), e)], axis=1)
+    boxes = np.concatenate([o, o + e], axis=1).astype(np.int64)
+    _say("case pool: batch of", nq, "boxes of", int(np.prod(e)), "voxels")
+    dev = _dev(host)
+    res, hists = tsa.region_batch(dev, boxes, 64)
+    hists = hists.cpu().numpy().view(np.uint64)
+    assert np.all(res["status"] == 0), np.unique(res["status"])
+    n3 = int(np.count_nonzero(res["flags"] & tsa.FLAG_PHASE3))
+    _say("case pool: boxes that took the third pass:", n3)
+    assert n3 > nq // 2  # the pool (16384 keys a box) holds fewer than 80 such boxes
+    _say("case pool: oracle over every box")
+    want, counts = oracle.stats_boxes(host, boxes, 64)
+    for i in range(nq):
+        r = {k: res[i][k].item() for k in res.dtype.names}
+        check_moments(r, want[i], "f32", f"pool q{i}")
+        check_median(r["median"], want[i]["median"], "f32", f"pool q{i}")
+        check_hist(hists[i], None, counts[i], None, f"pool q{i}")
+
+
+def test_batch_bounded_wait_gives_up_cleanly():
+    """The persistent kernel's bounded waits, forced from the host to give up
+    at their first poll: the kernel still exits, every box that needed its
+    second phase reports TSA_EDEVICE, boxes finished in their first phase
+    (constant or all-NaN boxes) keep their results, and the next batch on the
+    same workspace is correct again."""
+    spec = synth.scaled(synth.SPECS["c1"], 96, 64, 48)
+    host, _ = synth.generate(spec)
+    host[:8, :8, :16] = np.float32(2.5)  # a constant corner
+    host[40:44, 0:4, 0:8] = np.nan       # an all-NaN corner
+    boxes = _boxes((96, 64, 48), 60, seed=9, lo=2, hi=40)
+    const_box = np.array([[0, 0, 0, 16, 8, 8], [0, 0, 40, 8, 4, 44]], dtype=np.int64)
+    boxes = np.concatenate([boxes, const_box])
+    dev = _dev(host)
+    lib = tsa.capi().lib
+    lib.tsa_internal_batch_wait_limit.argtypes = [ctypes.c_int32]
+    lib.tsa_internal_batch_wait_limit(0)
+    try:
+        _say("case wait limit 0")
+        res, _ = tsa.region_batch(dev, boxes, 32)
+    finally:
+        lib.tsa_internal_batch_wait_limit(-1)
+    for i, b in enumerate(boxes):
+        want = oracle.stats(host, 32, tuple(int(v) for v in b))
+        r = {k: res[i][k].item() for k in res.dtype.names}
+        if want["count"] == 0 or np.float32(want["min"]).tobytes() == np.float32(want["max"]).tobytes():
+            assert r["status"] == 0, (i, b, r)
+            check_moments(r, want, "f32", f"wait q{i}")
+            check_median(r["median"], want["median"], "f32", f"wait q{i}")
+        else:
+            assert r["status"] == tsa.TSA_EDEVICE, (i, b, r)
+    _say("case wait limit restored")
+    _check_batch(host, dev, boxes, 32, what="after wait limit")

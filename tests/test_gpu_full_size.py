@@ -1,6 +1,5 @@
 """Full-size workloads in the launch configuration the benchmark times, checked
 on sampled outputs the oracle computes one by one."""
-import os
 import sys
 
 import numpy as np
@@ -21,9 +20,22 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def test_c4_region_batch_sampled():
+def _check_box_results(res, hists, want, counts, what, idx=None):
+    """GPU batch results against oracle.stats_boxes output, query by query."""
+    idx = range(len(want)) if idx is None else idx
+    for i in idx:
+        w = want[i]
+        r = {k: res[i][k].item() for k in res.dtype.names}
+        check_moments(r, w, "f32", f"{what} q{i}")
+        check_median(r["median"], w["median"], "f32", f"{what} q{i}")
+        assert bool(r["flags"] & tsa.FLAG_HIST_SKIPPED) == w["hist_skipped"], (what, i)
+        if not w["hist_skipped"]:
+            check_hist(hists[i], None, counts[i], None, f"{what} q{i}")
+
+
+def test_c4_region_batch_every_query():
     """4096 boxes on the resident 2048^3 cube (the benchmark's batch, default
-    tuning): a spread of queries (largest, smallest, random) against the oracle."""
+    tuning), every query against the oracle."""
     spec = synth.SPECS["c4"]
     _say("case c4: generating 2048^3")
     host, _ = synth.generate(spec)
@@ -32,27 +44,18 @@ def test_c4_region_batch_sampled():
     _say("case c4: batch")
     res, hists = tsa.region_batch(dev, boxes, 256)
     hists = hists.cpu().numpy().view(np.uint64)
-    vol = np.prod(boxes[:, 3:] - boxes[:, :3], axis=1)
-    rng = np.random.default_rng(3)
-    pick = sorted(set([int(np.argmax(vol)), int(np.argmin(vol))] + list(rng.choice(4096, 10, replace=False))))
     assert np.all(res["status"] == 0)
-    for i in pick:
-        b = tuple(int(v) for v in boxes[i])
-        _say("case c4 query", i, b, int(vol[i]))
-        want = oracle.stats(host, 256, b)
-        r = {k: res[i][k].item() for k in res.dtype.names}
-        check_moments(r, want, "f32", f"c4 q{i}")
-        check_median(r["median"], want["median"], "f32", f"c4 q{i}")
-        assert not want["hist_skipped"]
-        check_hist(hists[i], None, want["counts"], None, f"c4 q{i}")
+    _say("case c4: oracle over every box")
+    want, counts = oracle.stats_boxes(host, boxes, 256)
+    _check_box_results(res, hists, want, counts, "c4")
 
 
 def test_c2_minimap_spectrum_rank_sampled():
     """The benchmark's other workloads on the resident 1024x1024x1280 cube, in
-    the configuration it times: the 30^3 mini-map (52675 cells, 64 bins) and
-    its 3-sigma counts, the spectrum tool's 16384 sight lines x 2560 samples,
-    and the 0.9-quantile and MAD, checked on sampled outputs the oracle
-    computes one by one (quantile and MAD in full)."""
+    the configuration it times: the 30^3 mini-map (52675 cells, 64 bins, every
+    cell against the oracle) and its 3-sigma counts (sampled cells), the
+    spectrum tool's 16384 sight lines x 2560 samples (sampled rays), and the
+    0.9-quantile and MAD in full."""
     import bench
     spec = synth.SPECS["c2"]
     _say("case c2 (minimap/spectrum/rank): generating")
@@ -65,16 +68,11 @@ def test_c2_minimap_spectrum_rank_sampled():
     boxes = oracle.minimap_cells(dims, cell)
     assert len(res) == len(boxes) == 52675 and np.all(res["status"] == 0)
     rng = np.random.default_rng(5)
-    pick = sorted(set([0, len(boxes) - 1, 34, 35 * 35 - 1] + list(rng.choice(len(boxes), 12, replace=False))))
+    pick = sorted(set([0, len(boxes) - 1, 34, 35 * 35 - 1] + list(rng.choice(len(boxes), 200, replace=False))))
     h = hists.cpu().numpy().view(np.uint64)
-    for i in pick:
-        b = tuple(int(v) for v in boxes[i])
-        want = oracle.stats(host, nbins, b)
-        r = {kk: res[i][kk].item() for kk in res.dtype.names}
-        check_moments(r, want, "f32", f"c2 cell {i}")
-        check_median(r["median"], want["median"], "f32", f"c2 cell {i}")
-        if not want["hist_skipped"]:
-            check_hist(h[i], None, want["counts"], None, f"c2 cell {i}")
+    _say("case c2: oracle over every cell")
+    want, counts = oracle.stats_boxes(host, boxes, nbins)
+    _check_box_results(res, h, want, counts, "c2 cell")
     _say("case c2: 3-sigma counts")
     above = tsa.sigma_count(dev, cell, cells_dev, k)
     check_sigma_counts(host, above, cell, k, "c2 sigma", cells=pick)
@@ -99,33 +97,46 @@ def test_c2_minimap_spectrum_rank_sampled():
     check_median(mad, wmad, "f32", "c2 MAD")
 
 
-@pytest.mark.skipif(os.environ.get("TSA_TEST_C3") != "1",
-                    reason="206 GB cube, about a minute to generate: set TSA_TEST_C3=1 to run")
+C3_HBM_BYTES = 210 * 10**9
+
+
+@pytest.mark.timeout(1200)
 def test_c3_full_size_206gb():
     """The 4096x4096x3072 float32 cube (206 GB) resident on one GPU, 65536
-    bins: whole-cube results checked by invariants that hold at any size
-    (count + nan_count = N, the generator's NaN count, histogram total =
-    count, extremes bound every slab's), and two z-slabs checked against the
-    oracle on every output."""
-    import bench
+    bins, the benchmark's call: every output of the whole cube against the
+    streaming oracle (the cube regenerated slab by slab on the host; pass 1
+    uploads the same slabs to the device), plus one z-slab as a region."""
+    free, _ = torch.cuda.mem_get_info(0)
+    if free < C3_HBM_BYTES:
+        pytest.skip(f"needs {C3_HBM_BYTES / 1e9:.0f} GB of free device memory, {free / 1e9:.0f} GB free")
     spec = synth.SPECS["c3"]
-    _say("case c3: generating on the device")
-    dev, nan = bench.generate_on_device(synth, torch, spec)
+    dev = torch.empty((spec.nz, spec.ny, spec.nx), dtype=torch.float32, device="cuda:0")
+
+    def upload(z0, z1, arr):
+        dev[z0:z1].copy_(torch.from_numpy(arr))
+
+    _say("case c3: oracle pass 1 uploads the cube slab by slab")
+    want = oracle.stats_streaming(spec, 65536, on_slab=upload, log=_say)
+    torch.cuda.synchronize()
     N = dev.numel()
     _say("case c3: gpu stats, 65536 bins")
     res, counts, outl = tsa.stats(dev, 65536)
     assert res["status"] == 0
-    assert res["count"] + res["nan_count"] == N and res["nan_count"] == nan
-    assert int(counts.sum().item()) == res["count"] and int(outl.sum().item()) == 0
-    rng = np.random.default_rng(9)
-    for z0 in sorted(rng.choice(spec.nz - 8, 2, replace=False)):
-        z0 = int(z0)
-        box = (0, 0, z0, spec.nx, spec.ny, z0 + 8)
-        _say("case c3: slab", box)
-        host, _ = synth.generate(spec, z0, z0 + 8)
-        want = oracle.stats(host, 65536)
-        got, c, o = tsa.stats(dev, 65536, box)
-        check_moments(got, want, "f32", f"c3 slab {z0}")
-        check_median(got["median"], want["median"], "f32", f"c3 slab {z0}")
-        check_hist(c, o, want["counts"], want["outliers"], f"c3 slab {z0}")
-        assert res["min"] <= want["min"] and want["max"] <= res["max"]
+    assert res["count"] + res["nan_count"] == N and res["nan_count"] == want["generator_nan"]
+    check_moments(res, want, "f32", "c3")
+    check_median(res["median"], want["median"], "f32", "c3")
+    assert not want["hist_skipped"]
+    check_hist(counts, outl, want["counts"], want["outliers"], "c3")
+    _say("case c3: moments alone and the histogram alone")
+    check_moments(tsa.moments(dev), want, "f32", "c3 tsa_moments")
+    c, o = tsa.histogram(dev, want["min"], want["max"], 65536)
+    check_hist(c, o, want["counts"], want["outliers"], "c3 tsa_histogram")
+    z0 = 1531
+    box = (0, 0, z0, spec.nx, spec.ny, z0 + 8)
+    _say("case c3: slab", box)
+    host, _ = synth.generate(spec, z0, z0 + 8)
+    w = oracle.stats_exact(host, 65536)
+    got, c, o = tsa.stats(dev, 65536, box)
+    check_moments(got, w, "f32", f"c3 slab {z0}")
+    check_median(got["median"], w["median"], "f32", f"c3 slab {z0}")
+    check_hist(c, o, w["counts"], w["outliers"], f"c3 slab {z0}")

@@ -90,3 +90,28 @@ def test_mad_int16_and_edges():
     assert math.isnan(gm) and math.isnan(gmad) and gn == 0
     ties = np.float32([1, 1, 1, 2, 2, 3, 10, np.nan, -0.0, 0.0])
     assert tsa.mad(_dev(ties)) == oracle.mad(ties)
+
+
+def test_mad_infinite_median():
+    """A value equal to an infinite median deviates by zero (no NaN
+    deviations), as the oracle defines it."""
+    cases = {
+        "inf3_1": np.float32([np.inf, np.inf, np.inf, 1]),
+        "minf2_0": np.float32([-np.inf, -np.inf, 0]),
+        "inf_majority_nan": np.float32([1, 2, np.inf, np.inf, np.inf, np.nan]),
+        "finite_median_infs": np.float32([1, 2, 3, np.inf, -np.inf]),
+    }
+    rng = np.random.default_rng(17)
+    big = rng.standard_normal(50000).astype(np.float32)
+    big[rng.random(big.size) < 0.6] = np.inf
+    big[rng.random(big.size) < 0.01] = np.nan
+    cases["inf_majority_50k"] = big
+    neg = -big
+    cases["minf_majority_50k"] = neg
+    for name, x in cases.items():
+        _say("case mad inf", name)
+        want = oracle.mad(x)
+        got = tsa.mad(_dev(x))
+        assert got[2] == want[2], (name, got, want)
+        check_median(got[0], want[0], "f32", f"{name} median")
+        check_median(got[1], want[1], "f32", f"{name} mad")

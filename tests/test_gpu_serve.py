@@ -144,3 +144,40 @@ def test_bad_requests():
         srv.drain(30.0)
         r = srv.poll(4)
         assert len(r) == 1 and r[0].result.status == tsa.TSA_EINVAL and r[0].tag == 3
+
+
+def test_scratch_budget_limits_admission():
+    """A scratch budget of three region requests: admission waits on the
+    budget (the slot limit is far above it), the budget in use never exceeds
+    it, every answer equals the same request served alone, and a request that
+    costs more than the whole budget is refused at submission (TSA_ENOMEM)
+    instead of holding up its class."""
+    hosts = _cubes()
+    devs = [torch.from_numpy(h).to("cuda:0") for h in hosts]
+    reqs = [r for r in _workload(hosts, 150, seed=7, full_frac=0.0)]
+    with serve.Server(max_batch=16, region_lanes=2, max_admitted=4096, region_nbins=32, full_nbins=256) as probe:
+        cost = probe.stats()["region_cost"]
+    budget = 3 * cost
+    with serve.Server(max_batch=16, region_lanes=2, max_admitted=4096, region_nbins=32, full_nbins=256,
+                      scratch_bytes=budget) as srv:
+        ids = [srv.add_cube(d) for d in devs]
+        # a full-cube request needs the full-cube workspace: far above three region requests
+        with pytest.raises(tsa.TsaError) as e:
+            srv.submit(srv.request(ids[0], serve.REQ_FULL_MEDIAN, None))
+        assert e.value.status == tsa.TSA_ENOMEM
+        mk, mh = _make(srv, ids, reqs, 32, 256)
+        _say("case serve scratch budget", budget)
+        out = srv.replay(mk, serve.poisson_arrivals(50000.0, len(mk), seed=2))
+        st = srv.stats()
+        _say("server stats", st)
+        assert st["scratch_bytes"] == budget and 0 < st["budget_peak"] <= budget
+        assert st["admission_waits"] > 0 and st["max_batch"] <= 3
+        assert st["finished"] == st["submitted"] == len(reqs)
+        alone_mk, alone_h = _make(srv, ids, reqs, 32, 256)
+        for i, r in enumerate(alone_mk):
+            srv.submit(r)
+            srv.drain(60.0)
+            a = srv.poll(4)
+            assert len(a) == 1 and out[i].status == 0
+            assert _same(a[0], out[i]), (i, reqs[i])
+            assert np.array_equal(alone_h[i], mh[i]), i
