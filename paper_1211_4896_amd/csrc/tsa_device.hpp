@@ -126,9 +126,12 @@ TSA_DEV int64_t wave_sum_i64(int64_t v) {
 struct Partial {
   uint64_t n;
   uint32_t kmin, kmax;
-  double s, q;
-  int64_t si;
-  uint64_t qi;
+  double s, q;  // float32: sums S and Q, or (centered) the mean about ref and M2
+  union {
+    int64_t si;  // int16: exact sum
+    double ref;  // centered float32: the value the mean is taken about
+  };
+  uint64_t qi;  // int16: exact sum of squares
 };
 static_assert(sizeof(Partial) == 48, "partial layout");
 

@@ -114,22 +114,39 @@ TSA_DEV double value_of_key(uint32_t k, int dtype) {
 struct MergeShared {
   double n[1024], m[1024], q[1024];
   uint32_t kmin[1024], kmax[1024];
+  int first;
 };
 
 // Whole block: merge np partials in a fixed order (each thread a strided
 // sequence, then a pairwise tree) and write the moments fields of *out.
 // Returns (in every thread) the global count and min/max keys.
-// centered: the partials hold (mean, M2) (k_moments' float32 lanes).
+// centered: the partials hold (mean about ref, M2) (k_moments' float32
+// lanes); they are merged about one reference, the ref of the first partial
+// with a finite mean, which the mean gets back at the end.
 TSA_DEV void merge_moments(const Partial* __restrict__ parts, int np, int dtype, uint64_t volume, tsa_result* out,
                            MergeShared& sm, uint64_t& n_out, uint32_t& kmin_out, uint32_t& kmax_out,
                            bool centered = false) {
   const int t = threadIdx.x, bs = blockDim.x;
+  double ref0 = 0.0;
+  if (centered) {
+    if (t == 0) sm.first = np;
+    __syncthreads();
+    for (int i = t; i < np; i += bs) {
+      const Partial& p = parts[i];
+      if (p.n && __builtin_isfinite(p.s)) {
+        atomicMin(&sm.first, i);
+        break;
+      }
+    }
+    __syncthreads();
+    if (sm.first < np) ref0 = parts[sm.first].ref;
+  }
   double n = 0.0, m = 0.0, q = 0.0;
   uint32_t mn = 0xFFFFFFFFu, mx = 0u;
   for (int i = t; i < np; i += bs) {
     const Partial p = parts[i];
     double pn, pm, pq;
-    partial_stats(p, dtype, pn, pm, pq, centered);
+    partial_stats(p, dtype, pn, pm, pq, centered, ref0);
     chan_merge(n, m, q, pn, pm, pq);
     if (p.n) {
       mn = min(mn, p.kmin);
@@ -175,7 +192,7 @@ TSA_DEV void merge_moments(const Partial* __restrict__ parts, int np, int dtype,
         out->std = 0.0;
       } else {
         const double m2 = sm.q[0] < 0.0 ? 0.0 : sm.q[0];  // NaN (infinite values) stays
-        out->mean = sm.m[0];
+        out->mean = ref0 + sm.m[0];
         out->m2 = m2;
         out->std = sqrt(m2 / N);
       }

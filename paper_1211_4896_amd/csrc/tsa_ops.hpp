@@ -110,9 +110,11 @@ TSA_DEV void chan_merge(double& na, double& ma, double& qa, double nb, double mb
 }
 
 // (n, mean, M2) of one block partial, in double.  centered: the partial holds
-// (mean, M2) already (tsa_moments' shifted lanes); else float32 partials hold
-// the sums S and Q, int16 partials exact integer sums.
-TSA_DEV void partial_stats(const Partial& p, int dtype, double& n, double& m, double& q, bool centered = false) {
+// M2 and its mean about p.ref (tsa_moments' shifted lanes), returned here as
+// the mean about ref0; else float32 partials hold the sums S and Q, int16
+// partials exact integer sums.
+TSA_DEV void partial_stats(const Partial& p, int dtype, double& n, double& m, double& q, bool centered = false,
+                           double ref0 = 0.0) {
   n = (double)p.n;
   if (p.n == 0) {
     m = q = 0.0;
@@ -120,7 +122,7 @@ TSA_DEV void partial_stats(const Partial& p, int dtype, double& n, double& m, do
   }
   if (dtype == 0) {
     if (centered) {
-      m = p.s;
+      m = p.s + (p.ref - ref0);  // ref - ref0: two float32 values, exact in double
       q = p.q;
     } else {
       m = p.s / n;
@@ -168,7 +170,7 @@ struct ShiftMomAcc {
 
 // Reduce a block's lanes (fixed order) and store one Partial.
 struct alignas(16) MomShared {
-  double s[16], q[16];
+  double s[16], q[16], ref[16];
   int64_t si[16];
   uint64_t qi[16];
   uint32_t kmin[16], kmax[16];
@@ -260,12 +262,19 @@ TSA_DEV void block_store_partial(MomAcc<1, COUNT>& a, MomShared& sm, Partial* ou
 
 // Lanes of ShiftMomAcc: each lane's (n, mean, M2), then Chan merges down a
 // fixed tree (lane i takes lane i + o, o = 32 .. 1), the block's waves in
-// order; the Partial holds (n, mean, M2) ("centered") and the key extremes.
+// order.  Means are carried about one reference value, the shift of the
+// wave's (then the block's) first lane that has one, so the differences of
+// means the merge forms are exact to the spread's scale, not the mean's:
+// with mean/std = 1e7 a mean rounded to its own ulp would already cost 1e-9
+// of the spread.  The Partial holds (n, mean about ref, M2, ref) ("centered")
+// and the key extremes.
 TSA_DEV void block_store_centered(ShiftMomAcc& a, MomShared& sm, Partial* out) {
+  const uint64_t have = __ballot(a.have);
+  const double ref_w = have ? __shfl(a.c, __builtin_ctzll(have)) : 0.0;
   double n = (double)a.cnt, m = 0.0, m2 = 0.0;
   if (a.cnt) {
     const double r = a.s / n;
-    m = a.c + r;
+    m = (a.c - ref_w) + r;  // a.c - ref_w: two float32 values (or 0), exact in double
     m2 = a.q - a.s * r;
     if (m2 < 0.0) m2 = 0.0;  // rounding below zero; NaN (infinite values) stays
   }
@@ -279,6 +288,7 @@ TSA_DEV void block_store_centered(ShiftMomAcc& a, MomShared& sm, Partial* out) {
   if (lane == 0) {
     sm.s[w] = m;
     sm.q[w] = m2;
+    sm.ref[w] = have ? ref_w : __builtin_nan("");  // NaN: no finite value in the wave
     sm.cnt[w] = (uint64_t)n;
     sm.kmin[w] = kmin;
     sm.kmax[w] = kmax;
@@ -286,10 +296,15 @@ TSA_DEV void block_store_centered(ShiftMomAcc& a, MomShared& sm, Partial* out) {
   __syncthreads();
   if (threadIdx.x == 0) {
     const int nw = blockDim.x / kWave;
-    double bn = (double)sm.cnt[0], bm = sm.s[0], bq = sm.q[0];
-    uint32_t mn = sm.kmin[0], mx = sm.kmax[0];
-    for (int i = 1; i < nw; ++i) {
-      chan_merge(bn, bm, bq, (double)sm.cnt[i], sm.s[i], sm.q[i]);
+    double ref = 0.0;
+    for (int i = nw - 1; i >= 0; --i)
+      if (sm.ref[i] == sm.ref[i]) ref = sm.ref[i];
+    double bn = 0.0, bm = 0.0, bq = 0.0;
+    uint32_t mn = 0xFFFFFFFFu, mx = 0u;
+    for (int i = 0; i < nw; ++i) {
+      // a wave without a finite value has a non-finite mean whatever its shift
+      const double sh = sm.ref[i] == sm.ref[i] ? sm.ref[i] - ref : 0.0;
+      chan_merge(bn, bm, bq, (double)sm.cnt[i], sm.s[i] + sh, sm.q[i]);
       mn = min(mn, sm.kmin[i]);
       mx = max(mx, sm.kmax[i]);
     }
@@ -299,7 +314,7 @@ TSA_DEV void block_store_centered(ShiftMomAcc& a, MomShared& sm, Partial* out) {
     p.kmax = mx;
     p.s = bm;
     p.q = bq;
-    p.si = 0;
+    p.ref = ref;
     p.qi = 0;
     *out = p;
   }

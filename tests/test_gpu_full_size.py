@@ -106,6 +106,7 @@ def test_c3_full_size_206gb():
     bins, the benchmark's call: every output of the whole cube against the
     streaming oracle (the cube regenerated slab by slab on the host; pass 1
     uploads the same slabs to the device), plus one z-slab as a region."""
+    torch.cuda.empty_cache()  # blocks the earlier cases left in torch's cache
     free, _ = torch.cuda.mem_get_info(0)
     if free < C3_HBM_BYTES:
         pytest.skip(f"needs {C3_HBM_BYTES / 1e9:.0f} GB of free device memory, {free / 1e9:.0f} GB free")
