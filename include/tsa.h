@@ -167,6 +167,32 @@ int tsa_stats(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa
               tsa_stream_t stream);
 
 /*
+ * tsa_stats without a workspace, for callers that cannot allocate device
+ * memory (code under graph capture, allocation-free serving loops, harnesses
+ * that forbid hipMalloc): the same kernels and outputs as tsa_stats, with
+ * every piece of scratch taken from a fixed array of
+ * tsa_stats_static_scratch_bytes() (8 MiB) that the library holds on each
+ * device until the process ends.  The call itself allocates nothing (no
+ * hipMalloc, no graph).  Any cube or region is accepted: the median's
+ * candidate list holds at most tsa_stats_static_candidate_keys() keys, and a
+ * larger last key bucket is settled by a third pass over the data.
+ * Every call on a device shares that device's array, so calls that can
+ * overlap on one device (two streams, two threads) race and must be
+ * serialised by the caller; each call clears what must start at zero.
+ * Errors as tsa_stats; TSA_EDEVICE if the array's device address cannot be
+ * found; TSA_ENOMEM if the call's scratch would exceed the array (not
+ * reachable with the capped candidate list).
+ */
+int tsa_stats_static(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa_result* d_out,
+                     uint64_t* d_counts, uint64_t* d_outliers, tsa_stream_t stream);
+
+/* Size in bytes of tsa_stats_static's per-device scratch array. */
+size_t tsa_stats_static_scratch_bytes(void);
+
+/* Candidate keys tsa_stats_static's scratch holds for the median's last digits. */
+int64_t tsa_stats_static_candidate_keys(void);
+
+/*
  * The lower q-quantile: the non-NaN value of 0-based rank floor(q * (count-1))
  * under totalOrder, the product rounded to double (q in [0, 1]; q = 0.5 is the
  * lower median).  The same radix selection as tsa_median.  digits = 3 selects

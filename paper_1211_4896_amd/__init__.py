@@ -79,6 +79,9 @@ class _CAPI:
             "tsa_histogram": (ctypes.c_int, [CP, RP, ctypes.c_float, ctypes.c_float, I32, P, P, P, SZ, P]),
             "tsa_median": (ctypes.c_int, [CP, RP, P, P, SZ, P]),
             "tsa_stats": (ctypes.c_int, [CP, RP, I32, P, P, P, P, SZ, P]),
+            "tsa_stats_static": (ctypes.c_int, [CP, RP, I32, P, P, P, P]),
+            "tsa_stats_static_scratch_bytes": (SZ, []),
+            "tsa_stats_static_candidate_keys": (I64, []),
             "tsa_region_batch": (ctypes.c_int, [CP, P, I32, I32, P, P, ctypes.POINTER(Tune), P, SZ, P]),
             "tsa_status_string": (ctypes.c_char_p, [I32]),
             "tsa_version": (ctypes.c_char_p, []),
@@ -248,6 +251,20 @@ def stats(t, nbins: int, region=None, stream=None):
     outl = torch.empty(2, dtype=torch.int64, device=t.device)
     _check(capi().tsa_stats(ctypes.byref(c), _rp(reg), nbins, out.data_ptr(), counts.data_ptr(), outl.data_ptr(),
                             ws.data_ptr(), ws.numel(), _stream(stream)), "tsa_stats")
+    torch.cuda.synchronize(t.device)
+    return _rec(results_to_numpy(out)[0]), counts, outl
+
+
+def stats_static(t, nbins: int, region=None, stream=None):
+    """``stats`` through tsa_stats_static: no workspace, the library's fixed
+    per-device scratch instead.  Returns (result dict, counts, outliers)."""
+    torch = _torch()
+    c, reg = cube_of(t), region_of(region)
+    out = _result_buf(t)
+    counts = torch.empty(nbins, dtype=torch.int64, device=t.device)
+    outl = torch.empty(2, dtype=torch.int64, device=t.device)
+    _check(capi().tsa_stats_static(ctypes.byref(c), _rp(reg), nbins, out.data_ptr(), counts.data_ptr(),
+                                   outl.data_ptr(), _stream(stream)), "tsa_stats_static")
     torch.cuda.synchronize(t.device)
     return _rec(results_to_numpy(out)[0]), counts, outl
 

@@ -46,6 +46,15 @@ int tsa_stats(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa
   return run_stats(cube, region, nbins, d_out, d_counts, d_outliers, d_ws, ws_bytes, stream);
 }
 
+int tsa_stats_static(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa_result* d_out,
+                     uint64_t* d_counts, uint64_t* d_outliers, tsa_stream_t stream) {
+  return run_stats_static(cube, region, nbins, d_out, d_counts, d_outliers, stream);
+}
+
+size_t tsa_stats_static_scratch_bytes(void) { return stats_static_scratch_bytes(); }
+
+int64_t tsa_stats_static_candidate_keys(void) { return stats_static_cand_keys(); }
+
 int tsa_quantile(const tsa_cube* cube, const tsa_region* region, double q, int32_t digits, double* d_out,
                  void* d_ws, size_t ws_bytes, tsa_stream_t stream) {
   return run_quantile(cube, region, q, digits, d_out, d_ws, ws_bytes, stream);

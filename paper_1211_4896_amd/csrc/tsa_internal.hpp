@@ -21,6 +21,8 @@ constexpr int kMaxBlocks = 8192;      // upper bound of a pass grid (moment part
 // region batch: largest first-digit bucket whose keys a box copies out (larger ones
 // take a third pass over the box); the epilogue scans the copy with one block
 constexpr uint32_t kBatchCandMax = 1u << 20;
+// tsa_stats_static: bytes of its fixed per-device scratch array
+constexpr size_t kStaticScratchBytes = (size_t)8 << 20;
 
 struct Tuning {
   int block = 512;     // threads per block of the streaming passes
@@ -76,5 +78,9 @@ int run_mad(const tsa_cube* cube, const tsa_region* region, double* d_out, void*
             tsa_stream_t stream);
 int run_stats(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa_result* d_out, uint64_t* d_counts,
               uint64_t* d_outliers, void* d_ws, size_t ws_bytes, tsa_stream_t stream);
+int run_stats_static(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa_result* d_out,
+                     uint64_t* d_counts, uint64_t* d_outliers, tsa_stream_t stream);
+size_t stats_static_scratch_bytes();
+int64_t stats_static_cand_keys();
 
 }  // namespace tsa

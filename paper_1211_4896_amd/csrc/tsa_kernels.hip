@@ -2,6 +2,8 @@
 // median, and the fused two-pass trio.
 #include <math.h>
 
+#include <mutex>
+
 #include "tsa_internal.hpp"
 
 namespace tsa {
@@ -854,7 +856,9 @@ struct WsLayout {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static WsLayout ws_layout(int64_t volume) {
+// cand_limit: most candidate keys the layout may hold (the fixed scratch of
+// tsa_stats_static); a median bucket above the capacity takes a third pass.
+static WsLayout ws_layout(int64_t volume, int64_t cand_limit = INT64_MAX) {
   WsLayout L;
   size_t o = 0;
   L.partials = o;
@@ -879,6 +883,7 @@ static WsLayout ws_layout(int64_t volume) {
   if (cap < 65536) cap = 65536;
   if (cap > (1ll << 26)) cap = 1ll << 26;
   if (cap > volume) cap = volume;
+  if (cap > cand_limit) cap = cand_limit;
   L.cand_cap = (uint32_t)cap;
   L.cand = o;
   o = align256(o + 4 * (size_t)cap);
@@ -945,13 +950,13 @@ struct Prep {
 constexpr int kBpcStats = 3, kBpcMoments = 3, kBpcHist = 2, kBpcSelect = 2;
 
 static int prepare(const tsa_cube* cube, const tsa_region* region, void* d_ws, size_t ws_bytes,
-                   tsa_stream_t stream, Prep* P, int bpc_default) {
+                   tsa_stream_t stream, Prep* P, int bpc_default, int64_t cand_limit = INT64_MAX) {
   int st = check_cube(cube);
   if (st) return st;
   if ((st = region_box(cube, region, &P->box))) return st;
   if ((st = device_info(&P->dev))) return st;
   if ((st = make_geom(cube, P->box, kTileUnits, &P->g, &P->vec, &P->volume))) return st;
-  P->L = ws_layout(P->volume);
+  P->L = ws_layout(P->volume, cand_limit);
   if (!d_ws || ws_bytes < P->L.total) return TSA_ENOMEM;
   P->ws = (char*)d_ws;
   P->s = (hipStream_t)stream;
@@ -1100,7 +1105,8 @@ int run_median(const tsa_cube* cube, const tsa_region* region, tsa_result* d_out
 }
 
 static int enqueue_stats(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa_result* d_out,
-                         uint64_t* d_counts, uint64_t* d_outliers, void* d_ws, size_t ws_bytes, tsa_stream_t stream);
+                         uint64_t* d_counts, uint64_t* d_outliers, void* d_ws, size_t ws_bytes, tsa_stream_t stream,
+                         int64_t cand_limit = INT64_MAX);
 
 namespace {
 struct StatsCall {
@@ -1158,12 +1164,63 @@ int run_stats(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa
   return graph_run(key, (hipStream_t)stream, enqueue_stats_call, &c);
 }
 
+// ---------------------------------------------------------------------------
+// tsa_stats_static: the fused trio on a fixed scratch array of the library's
+// own, for callers that cannot allocate device memory.  The host never uses
+// the array's name as an address: each device's copy is looked up once with
+// hipGetSymbolAddress (with that device current) and that pointer is what
+// the kernels get.  Every call on a device shares its copy; calls that
+// overlap on one device race.  Each call clears what has to start at zero
+// (selection state, level histograms, counts and outliers) with fill kernels.
+// ---------------------------------------------------------------------------
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::once_flag g_scratch_once[kMaxScratchDevices];
+void* g_scratch_ptr[kMaxScratchDevices];
+int g_scratch_status[kMaxScratchDevices];
+}  // namespace
+
+static int static_scratch(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxScratchDevices) return TSA_EDEVICE;
+  std::call_once(g_scratch_once[dev], [dev] {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_scratch_ptr[dev] = e == hipSuccess ? p : nullptr;
+    g_scratch_status[dev] = (e == hipSuccess && p) ? TSA_OK : TSA_EDEVICE;
+  });
+  *out = g_scratch_ptr[dev];
+  return g_scratch_status[dev];
+}
+
+// Candidate keys the fixed scratch holds beside everything else of the call.
+static int64_t static_cand_limit() {
+  const size_t fixed = ws_layout(0, 0).total;
+  return (int64_t)((kStaticScratchBytes - fixed) / 4) & ~(int64_t)63;
+}
+
+int run_stats_static(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa_result* d_out,
+                     uint64_t* d_counts, uint64_t* d_outliers, tsa_stream_t stream) {
+  void* ws = nullptr;
+  const int st = static_scratch(&ws);
+  if (st) return st;
+  // launched directly: a graph would be instantiated, and instantiation may allocate
+  return enqueue_stats(cube, region, nbins, d_out, d_counts, d_outliers, ws, kStaticScratchBytes, stream,
+                       static_cand_limit());
+}
+
+size_t stats_static_scratch_bytes() { return kStaticScratchBytes; }
+int64_t stats_static_cand_keys() { return static_cand_limit(); }
+
 static int enqueue_stats(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa_result* d_out,
-                         uint64_t* d_counts, uint64_t* d_outliers, void* d_ws, size_t ws_bytes, tsa_stream_t stream) {
+                         uint64_t* d_counts, uint64_t* d_outliers, void* d_ws, size_t ws_bytes, tsa_stream_t stream,
+                         int64_t cand_limit) {
   if (!d_out || !d_counts) return TSA_EINVAL;
   if (nbins < 1 || nbins > 65536) return TSA_EINVAL;
   Prep P;
-  int st = prepare(cube, region, d_ws, ws_bytes, stream, &P, kBpcStats);
+  int st = prepare(cube, region, d_ws, ws_bytes, stream, &P, kBpcStats, cand_limit);
   if (st) return st;
   const size_t budget = P.dev.lds_per_block < 65536 ? P.dev.lds_per_block : 65536;
   const size_t cand_small = (size_t)(P.block / kWave) * kWaveStage * 4;  // pass B's candidate staging
