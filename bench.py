@@ -1,20 +1,23 @@
 #!/usr/bin/env python3
 """Benchmark of the cube-statistics hot path on one MI355X.
 
-A step is one pass of the whole analysis path of the paper's Section 4 over
-the resident 1024x1024x1280 float32 cube (one GPU's share of a ~0.5 TB cube,
-the paper's load per GPU at 96 GPUs): global moments, the 4096-bin histogram
-over [min, max], and the exact lower median -- one tsa_stats call (two passes
-over the data plus small selection kernels).  Inputs are synthetic and seeded
-(noise + Gaussian sources + NaN slabs) and already resident in HBM when the
-timed region starts.
+A step is one pass of the whole analysis path of the paper's Section 4 over a
+resident float32 cube: global moments, the N-bin histogram over [min, max],
+and the exact lower median -- one tsa_stats call (two passes over the data
+plus small selection kernels).  The headline cube is the largest that fits one
+GPU: 4096x4096x3072 (206 GB in HBM, 65536 bins; the 8-way share of a 1.6 TB
+cube).  Inputs are synthetic and seeded (noise + Gaussian sources + NaN
+slabs) and already resident in HBM when the timed region starts.
 
 Prints one JSON line: whole-step throughput in GVoxel/s, the roofline entry of
 the dominant kernel (its duration measured with HIP events on its launch
-stream during the timed steps), the separate-call rates of the histogram and
-the median, and the CPU oracle timed on a bounded sample of the same cube.
+stream during the timed steps), the separate-call rates of the histogram,
+median and moments, the CPU oracle timed on a bounded sample of the same cube
+on the host's cores, and, as extra keys, the 1024x1024x1280 cube (one GPU's
+share at 96 GPUs), the 256^3 cube, the mini-map, the spectrum tool, batched
+region queries and the serving loop.
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 5]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--workload c3|c2|c1]
 """
 from __future__ import annotations
 
@@ -84,37 +87,110 @@ def _trace_read(lib) -> dict:
     return json.loads(buf.value.decode())
 
 
-def _cpu_baseline(host, nbins: int, target_s: float = 12.0) -> dict:
-    """The oracle (plain C + numpy selection, single-threaded) on the first z
-    slices of the same cube: moments, histogram over [min, max], median."""
+def _cpu_baseline(spec, nbins: int, target_s: float = 1.5, max_planes: int = 256) -> dict:
+    """The oracle timed on the host's cores: ``oracle.stats_exact`` (exact sums
+    for the moments, the histogram over [min, max], the lower median by a
+    two-level key count; the oracle the 206 GB cube is checked against),
+    threads over the values, on a z-slab from the middle of the same cube,
+    generated outside the timed region.  The slab grows until one run takes
+    about target_s seconds of wall time."""
     import oracle
+    import synth
 
-    plane = host.shape[1] * host.shape[2]
-    probe = max(1, (1 << 24) // plane)
+    threads = synth.default_threads()
+    plane = spec.nx * spec.ny
+    planes = max(1, (1 << 24) // plane)
+    while True:
+        z0 = max(0, spec.nz // 2 - planes // 2)
+        z1 = min(spec.nz, z0 + planes)
+        host, _ = synth.generate(spec, z0, z1)
+        t0 = time.perf_counter()
+        oracle.stats_exact(host, nbins, threads=threads)
+        dt = time.perf_counter() - t0
+        if dt >= target_s or planes >= max_planes or z1 - z0 == spec.nz:
+            break
+        planes = int(min(max_planes, max(planes + 1, planes * target_s / max(dt, 1e-3) * 1.1)))
+        del host
+    nvox = (z1 - z0) * plane
+    return {"value": round(nvox / dt / 1e9, 4), "unit": "GVoxel/s", "cores": threads, "kind": "oracle",
+            "sample": f"z-slices [{z0}, {z1}) of the {spec.nx}x{spec.ny}x{spec.nz} cube ({nvox} voxels), "
+                      f"oracle.stats_exact on {threads} threads: moments (exact sums) + {nbins}-bin histogram over "
+                      f"[min,max] + lower median (two-level 16+16-bit key count), {dt:.2f} s wall",
+            "host_cpus": os.cpu_count()}
+
+
+def _workload_text(name: str, spec, nbins: int) -> str:
+    return (f"{name}: {spec.nx}x{spec.ny}x{spec.nz} float32 cube ({spec.nx * spec.ny * spec.nz * 4 / 1e9:.1f} GB "
+            f"resident; seeded noise + {spec.n_sources} Gaussian sources + {spec.nan_frac:.1%} NaN slabs); moments + "
+            f"{nbins}-bin histogram over [min,max] + exact lower median (tsa_stats)")
+
+
+# algorithmic bytes of one launch of the streaming passes of tsa_stats: one read
+# of the cube plus the histogram the pass produces (8 bytes per bin)
+def _pass_bytes(kernel: str, N: int, nbins: int) -> float:
+    if kernel == "pass_a":
+        return 4.0 * N + 8.0 * 4096
+    if kernel in ("pass_b", "pass_bwin", "pass_b16"):
+        return 4.0 * N + 8.0 * nbins
+    return 4.0 * N
+
+
+def _timed_stats(tsa, torch, lib, dev, nbins: int, steps: int, warmup: int, workload: str) -> dict:
+    """warmup untimed tsa_stats calls, then exactly `steps` timed ones bracketed
+    by device synchronisation; per-kernel times from HIP events on the launch
+    stream (tsa_trace); the roofline entry of the dominant kernel."""
+    api = tsa.capi()
+    c = tsa.cube_of(dev)
+    cp = ctypes.byref(c)
+    ws = tsa.workspace(tsa.OP_STATS, dev, None, nbins)
+    out = torch.empty(72, dtype=torch.uint8, device=dev.device)
+    counts = torch.empty(nbins, dtype=torch.int64, device=dev.device)
+    outl = torch.empty(2, dtype=torch.int64, device=dev.device)
+    stream = torch.cuda.current_stream()
+    sh = stream.cuda_stream
+
+    def step():
+        st = api.tsa_stats(cp, None, nbins, out.data_ptr(), counts.data_ptr(), outl.data_ptr(), ws.data_ptr(),
+                           ws.numel(), sh)
+        if st != 0:
+            raise RuntimeError(f"tsa_stats failed: {tsa.status_string(st)}")
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    _trace(lib, True, cap=steps * 32)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    oracle.stats(host[:probe], nbins)
-    t_probe = time.perf_counter() - t0
-    nz = int(min(host.shape[0], max(probe, probe * target_s / max(t_probe, 1e-3))))
-    sample = host[:nz]
-    t0 = time.perf_counter()
-    oracle.stats(sample, nbins)
-    dt = time.perf_counter() - t0
-    nvox = nz * plane
-    # the three statistics one by one on the same sample
-    parts = {}
-    t0 = time.perf_counter()
-    mo = oracle.moments(sample)
-    parts["moments_s"] = round(time.perf_counter() - t0, 3)
-    t0 = time.perf_counter()
-    oracle.histogram(sample, float(mo["min"]), float(mo["max"]), nbins)
-    parts["histogram_s"] = round(time.perf_counter() - t0, 3)
-    t0 = time.perf_counter()
-    oracle.median(sample)
-    parts["median_s"] = round(time.perf_counter() - t0, 3)
-    return {"value": round(nvox / dt / 1e9, 6), "unit": "GVoxel/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {nz} of {host.shape[0]} z-slices ({nvox} voxels), moments + {nbins}-bin "
-                      f"histogram over [min,max] + lower median, {dt:.2f} s",
-            "parts": parts, "host_cpus": os.cpu_count()}
+    e0.record(stream)
+    for _ in range(steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3 / steps
+    ev_ms = e0.elapsed_time(e1) / steps
+    kern = _trace_read(lib)
+    _trace(lib, False)
+    res = tsa.results_to_numpy(out)[0]
+    if res["status"] != 0:
+        raise RuntimeError("device status %d" % res["status"])
+    N = dev.numel()
+    dom_name, (dom_n, dom_tot, _, _) = max(kern.items(), key=lambda kv: kv[1][1])
+    dom_avg_ms = dom_tot / dom_n
+    per_launch = _pass_bytes(dom_name, N, nbins)
+    achieved = per_launch / (dom_avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": _counter_traffic(dom_name, workload),
+                "kernel": dom_name, "avg_ms": round(dom_avg_ms, 4), "bytes_per_launch": per_launch}
+    probe = _read_probe(lib, dev, sh, torch)
+    roofline["achievable_read_GBps"] = probe["GBps"]
+    roofline["frac_of_achievable"] = round(achieved / probe["GBps"], 4)
+    hist_total = int(counts.sum().item()) + int(outl.sum().item())
+    return {"ms_per_step": wall_ms, "event_ms_per_step": round(ev_ms, 4), "roofline": roofline,
+            "kernels_ms": {k: round(v[1] / v[0], 4) for k, v in kern.items()}, "res": res,
+            "checks": {"count_plus_nan_is_N": int(res["count"]) + int(res["nan_count"]) == N,
+                       "hist_total_is_count": hist_total == int(res["count"])},
+            "api": api, "cp": cp, "sh": sh}
 
 
 def main():
@@ -122,21 +198,24 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2"])
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3"],
+                    help="headline cube: c3 = 4096x4096x3072 (206 GB, 65536 bins), c2 = 1024x1024x1280 "
+                         "(5.4 GB, 4096 bins), c1 = 256^3 (1024 bins)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ops", action="store_true", help="skip the separate-call measurements")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run 3 plain 1 GiB device copies (reference dispatches for byte counters)")
+    ap.add_argument("--no-c2", action="store_true", help="skip the 1024x1024x1280 cube and what runs on it "
+                                                         "(mini-map, spectrum) when it is not the headline")
     ap.add_argument("--no-region", action="store_true", help="skip the batched-vs-plain region queries (c4)")
     ap.add_argument("--region-reps", type=int, default=5)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run (c5)")
-    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--serve-warmup", type=float, default=10.0)
     ap.add_argument("--serve-qps", type=float, default=2000.0)
     ap.add_argument("--no-minimap", action="store_true", help="skip the mini-map + k-sigma measurement")
     ap.add_argument("--no-spectrum", action="store_true", help="skip the spectrum-tool measurement")
     ap.add_argument("--no-c1", action="store_true", help="skip the 256^3 cache-resident case")
-    ap.add_argument("--c3", action="store_true",
-                    help="also run the 4096x4096x3072 (206 GB) cube with 65536 bins (about a minute to generate)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this path does not shard)",
@@ -149,107 +228,79 @@ def main():
     import synth
     import paper_1211_4896_amd as tsa
 
-    nbins = {"c1": 1024, "c2": 4096}[args.workload]
-    spec = synth.SPECS[args.workload]
-    t0 = time.perf_counter()
-    host, nan = synth.generate(spec)
-    print(f"[bench] generated {spec.nx}x{spec.ny}x{spec.nz} in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
-          flush=True)
-    dev = torch.from_numpy(host).to("cuda:0")
-    torch.cuda.synchronize()
-    N = host.size
     lib = tsa.capi().lib
     lib.tsa_trace_enable.argtypes = [ctypes.c_int32, ctypes.c_int32]
     lib.tsa_trace_read.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
+    NBINS = {"c1": 1024, "c2": 4096, "c3": 65536}
 
-    c = tsa.cube_of(dev)
-    cp = ctypes.byref(c)
-    ws = tsa.workspace(tsa.OP_STATS, dev, None, nbins)
-    out = torch.empty(72, dtype=torch.uint8, device=dev.device)
-    counts = torch.empty(nbins, dtype=torch.int64, device=dev.device)
-    outl = torch.empty(2, dtype=torch.int64, device=dev.device)
-    stream = torch.cuda.current_stream()
-    sh = stream.cuda_stream
-    api = tsa.capi()
+    def load(name):
+        spec = synth.SPECS[name]
+        t0 = time.perf_counter()
+        if name == "c3":
+            dev, _ = generate_on_device(synth, torch, spec)
+        else:
+            host, _ = synth.generate(spec)
+            dev = torch.from_numpy(host).to("cuda:0")
+            del host
+        torch.cuda.synchronize()
+        print(f"[bench] {name}: generated {spec.nx}x{spec.ny}x{spec.nz} in {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
+        return spec, dev
 
-    def step():
-        st = api.tsa_stats(cp, None, nbins, out.data_ptr(), counts.data_ptr(), outl.data_ptr(), ws.data_ptr(),
-                           ws.numel(), sh)
-        if st != 0:
-            raise RuntimeError(f"tsa_stats failed: {tsa.status_string(st)}")
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    _trace(lib, True, cap=args.steps * 32)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        step()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall_ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    ev_ms = e0.elapsed_time(e1) / args.steps
-    kern = _trace_read(lib)
-    _trace(lib, False)
-    res = tsa.results_to_numpy(out)[0]
-    if res["status"] != 0:
-        raise RuntimeError("device status %d" % res["status"])
-
-    ms_per_step = wall_ms
-    value = N / (ms_per_step * 1e-3) / 1e9
-    # dominant kernel by total traced time
-    dom = max(kern.items(), key=lambda kv: kv[1][1])
-    dom_name, (dom_n, dom_tot, dom_min, dom_max) = dom
-    dom_avg_ms = dom_tot / dom_n
-    per_launch_bytes = {"pass_a": 4.0 * N + 8.0 * 4096, "pass_b": 4.0 * N + 8.0 * nbins}.get(dom_name, 4.0 * N)
-    achieved = per_launch_bytes / (dom_avg_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": _counter_traffic(dom_name, args.workload),
-                "kernel": dom_name, "avg_ms": round(dom_avg_ms, 4),
-                "bytes_per_launch": per_launch_bytes}
-
-    probe = _read_probe(lib, dev, sh, torch)
-    roofline["achievable_read_GBps"] = probe["GBps"]
-    roofline["frac_of_achievable"] = round(achieved / probe["GBps"], 4)
-
-    line = {"metric": METRIC, "value": round(value, 2), "unit": "GVoxel/s", "n_gpus": 1, "steps": args.steps,
-            "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
-            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-            "config": {"workload": f"{args.workload}: {spec.nx}x{spec.ny}x{spec.nz} float32 cube (seeded noise + "
-                                   f"{spec.n_sources} Gaussian sources + {spec.nan_frac:.1%} NaN slabs); moments + "
-                                   f"{nbins}-bin histogram over [min,max] + exact lower median (tsa_stats)",
-                       "voxels": N, "nbins": nbins, "parallelism": "1 GPU"},
-            "roofline": roofline,
-            "event_ms_per_step": round(ev_ms, 4),
-            "kernels_ms": {k: round(v[1] / v[0], 4) for k, v in kern.items()}}
-
+    head = args.workload
+    nbins = NBINS[head]
+    spec, dev = load(head)
+    N = dev.numel()
+    t = _timed_stats(tsa, torch, lib, dev, nbins, args.steps, args.warmup, head)
+    ms_per_step = t["ms_per_step"]
+    line = {"metric": METRIC, "value": round(N / (ms_per_step * 1e-3) / 1e9, 2), "unit": "GVoxel/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": _workload_text(head, spec, nbins), "voxels": N, "nbins": nbins, "parallelism": "1 GPU"},
+            "roofline": t["roofline"], "event_ms_per_step": t["event_ms_per_step"], "kernels_ms": t["kernels_ms"],
+            "checks": t["checks"]}
+    print(f"[bench] {head}: {ms_per_step:.3f} ms/step", file=sys.stderr, flush=True)
+    res = t["res"]
     if not args.no_ops:
-        line["ops"] = _separate_ops(tsa, api, dev, cp, N, float(res["min"]), float(res["max"]), nbins, sh)
+        line["ops"] = _separate_ops(tsa, t["api"], dev, t["cp"], N, float(res["min"]), float(res["max"]), nbins,
+                                    t["sh"])
     if args.calib_copy:
-        line["calib_copy_bytes"] = _calib_copy(lib, dev.device, sh)
-    if not args.no_c1:
+        line["calib_copy_bytes"] = _calib_copy(lib, dev.device, t["sh"])
+    if head != "c2":
+        del dev, t
+        torch.cuda.empty_cache()
+        dev = None
+        if not args.no_c2:
+            _, dev = load("c2")
+            t2 = _timed_stats(tsa, torch, lib, dev, 4096, args.steps, args.warmup, "c2")
+            line["c2"] = {"workload": _workload_text("c2", synth.SPECS["c2"], 4096),
+                          "ms_per_step": round(t2["ms_per_step"], 4),
+                          "gvoxel_s": round(dev.numel() / (t2["ms_per_step"] * 1e-3) / 1e9, 2),
+                          "roofline": t2["roofline"], "kernels_ms": t2["kernels_ms"], "checks": t2["checks"]}
+            if not args.no_ops:
+                r2 = t2["res"]
+                line["c2"]["ops"] = _separate_ops(tsa, t2["api"], dev, t2["cp"], dev.numel(), float(r2["min"]),
+                                                  float(r2["max"]), 4096, t2["sh"])
+            del t2
+    sh = torch.cuda.current_stream().cuda_stream
+    if not args.no_c1 and head != "c1":
         line["c1"] = _c1_bench(tsa, torch, synth, lib, sh)
-    if not args.no_minimap:
-        line["minimap"] = _minimap_bench(tsa, torch, api, lib, dev, sh, args.region_reps)
-    if not args.no_spectrum:
-        line["spectrum"] = _spectrum_bench(tsa, torch, np, synth, api, lib, dev, sh, args.region_reps)
-    del dev, ws
+    if dev is not None and dev.numel() == synth.SPECS["c2"].n:
+        api = tsa.capi()
+        if not args.no_minimap:
+            line["minimap"] = _minimap_bench(tsa, torch, api, lib, dev, sh, args.region_reps)
+        if not args.no_spectrum:
+            line["spectrum"] = _spectrum_bench(tsa, torch, np, synth, api, lib, dev, sh, args.region_reps)
+    dev = None
     torch.cuda.empty_cache()
     if not args.no_region:
         line["region_batch"] = _region_batch_bench(tsa, torch, np, synth, args.region_reps)
         torch.cuda.empty_cache()
     if not args.no_serve:
-        line["serving"] = _serving_bench(torch, np, synth, args.serve_seconds, args.serve_qps)
+        line["serving"] = _serving_bench(torch, np, synth, args.serve_seconds, args.serve_qps, args.serve_warmup)
         torch.cuda.empty_cache()
-    if args.c3:
-        del host
-        line["c3"] = _c3_bench(tsa, torch, np, synth, lib)
-        torch.cuda.empty_cache()
-    if not args.no_cpu_baseline and not args.c3:
-        line["cpu_baseline"] = _cpu_baseline(host, nbins)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = _cpu_baseline(spec, nbins)
     print(json.dumps(line), flush=True)
 
 
@@ -476,7 +527,7 @@ def _spectrum_bench(tsa, torch, np, synth, api, lib, dev, sh, reps: int) -> dict
             "gathered_gb_s": round((32.0 * inside + 8.0 * ns) / (kms * 1e-3) / 1e9, 1)}
 
 
-def _serving_bench(torch, np, synth, seconds: float, qps: float) -> dict:
+def _serving_bench(torch, np, synth, seconds: float, qps: float, warm: float = 10.0) -> dict:
     """c5: open-loop Poisson arrivals over three resident cubes (float32 1024^3,
     float32 2048x2048x1024, int16 2048^3): 90% region requests (c4 boxes), 10%
     full-cube requests (half 4096-bin histograms over the cube's [min,max],
@@ -490,7 +541,6 @@ def _serving_bench(torch, np, synth, seconds: float, qps: float) -> dict:
         devs.append(torch.from_numpy(host).to("cuda:0"))
         del host
     torch.cuda.synchronize()
-    warm = 2.0
     n = int((warm + seconds) * qps)
     rng = np.random.default_rng(77)
     t_arr = serve.poisson_arrivals(qps, n, seed=78)
@@ -588,64 +638,31 @@ def _c1_bench(tsa, torch, synth, lib, sh, reps: int = 20) -> dict:
             "cold_ms": round(cold, 4), "cold_gvoxel_s": round(N / (cold * 1e-3) / 1e9, 1)}
 
 
-def generate_on_device(synth, torch, spec, chunk: int = 32):
-    """A cube generated in z-slabs straight into one device tensor (the host
-    holds one slab at a time).  Returns (tensor, nan count)."""
-    dev = torch.empty((spec.nz, spec.ny, spec.nx), dtype=torch.float32 if spec.dtype == "f32" else torch.int16,
-                      device="cuda:0")
+def generate_on_device(synth, torch, spec, planes: int = 16):
+    """A cube generated in z-slabs straight into one device tensor: the host
+    generates the next slab into one of two pinned buffers while the other's
+    copy to the device runs.  Returns (tensor, nan count)."""
+    dt = torch.float32 if spec.dtype == "f32" else torch.int16
+    dev = torch.empty((spec.nz, spec.ny, spec.nx), dtype=dt, device="cuda:0")
+    bufs = [torch.empty((planes, spec.ny, spec.nx), dtype=dt, pin_memory=True) for _ in range(2)]
+    copied = [None, None]
+    stream = torch.cuda.Stream()
     nan = 0
-    for z0 in range(0, spec.nz, chunk):
-        z1 = min(spec.nz, z0 + chunk)
-        part, n = synth.generate(spec, z0, z1)
-        dev[z0:z1].copy_(torch.from_numpy(part))
+    for i, z0 in enumerate(range(0, spec.nz, planes)):
+        z1 = min(spec.nz, z0 + planes)
+        b = i % 2
+        if copied[b] is not None:
+            copied[b].synchronize()  # this buffer's previous copy has finished
+        _, n = synth.generate(spec, z0, z1, out=bufs[b][: z1 - z0].numpy())
         nan += n
+        with torch.cuda.stream(stream):
+            dev[z0:z1].copy_(bufs[b][: z1 - z0], non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(stream)
+        copied[b] = ev
+    stream.synchronize()
     torch.cuda.synchronize()
     return dev, nan
-
-
-def _c3_bench(tsa, torch, np, synth, lib, reps: int = 5) -> dict:
-    """The 206 GB cube (4096x4096x3072 float32, 20000 sources with log-uniform
-    amplitudes, 0.1% NaN) resident on one GPU: tsa_stats with 65536 bins."""
-    spec = synth.SPECS["c3"]
-    nbins = 65536
-    t0 = time.perf_counter()
-    dev, nan = generate_on_device(synth, torch, spec)
-    t_gen = time.perf_counter() - t0
-    c = tsa.cube_of(dev)
-    cp = ctypes.byref(c)
-    api = tsa.capi()
-    ws = tsa.workspace(tsa.OP_STATS, dev, None, nbins)
-    out = torch.empty(72, dtype=torch.uint8, device=dev.device)
-    counts = torch.empty(nbins, dtype=torch.int64, device=dev.device)
-    outl = torch.empty(2, dtype=torch.int64, device=dev.device)
-    sh = torch.cuda.current_stream().cuda_stream
-
-    def step():
-        st = api.tsa_stats(cp, None, nbins, out.data_ptr(), counts.data_ptr(), outl.data_ptr(), ws.data_ptr(),
-                           ws.numel(), sh)
-        if st != 0:
-            raise RuntimeError(f"tsa_stats: {tsa.status_string(st)}")
-
-    step()
-    torch.cuda.synchronize()
-    _trace(lib, True, cap=reps * 32)
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        step()
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / reps
-    kern = _trace_read(lib)
-    _trace(lib, False)
-    r = tsa.results_to_numpy(out)[0]
-    N = dev.numel()
-    hist_total = int(counts.sum().item())
-    return {"workload": "c3: 4096x4096x3072 float32 cube (206 GB resident), 20000 sources A log-uniform [3,500], "
-                        "0.1% NaN; moments + 65536-bin histogram over [min,max] + exact median (tsa_stats)",
-            "voxels": N, "ms_per_step": round(ms, 3), "gvoxel_s": round(N / (ms * 1e-3) / 1e9, 1),
-            "kernels_ms": {k: round(v[1] / v[0], 4) for k, v in kern.items()},
-            "count_plus_nan_is_N": int(r["count"]) + int(r["nan_count"]) == N,
-            "nan_count_matches_generator": int(r["nan_count"]) == nan, "hist_total_is_count": hist_total == int(r["count"]),
-            "status": int(r["status"]), "generate_s": round(t_gen, 1)}
 
 
 def _read_probe(lib, dev, sh, torch, reps: int = 10) -> dict:
