@@ -5,8 +5,9 @@
  * Kilborn, "Tera-scale astronomical data analysis and visualization" (MNRAS,
  * arXiv 1211.4896), Section 4: global histogram (4.1), global mean and
  * standard deviation (4.2) and global median (4.3), over 3-D image cubes
- * held resident in GPU memory, plus batched sub-cube ("local, over small user
- * defined regions", Section 4 introduction) queries.
+ * held resident in GPU memory, plus batched queries over many small
+ * caller-chosen sub-cubes (the local statistics of the Section 4
+ * introduction).
  *
  * Conventions shared by every call
  * --------------------------------
@@ -14,7 +15,7 @@
  *    (RA, Dec, frequency as in the paper's survey cubes).  Element type float32
  *    or int16.  The cube pointer is a device pointer; the caller owns it and it
  *    must stay valid and unmodified until the stream reaches the end of the call.
- *  - NULL voxels (Section 4: "special handling for the NULL data points") are
+ *  - NULL voxels (Section 4 asks for them to be left out) are
  *    NaN; they are excluded from every statistic and counted in nan_count.
  *    +-inf are ordinary values.  int16 cubes have no NULL value.
  *  - Ordering is IEEE-754 totalOrder on non-NaN values (-0 < +0); min, max and
@@ -220,7 +221,7 @@ int tsa_mad(const tsa_cube* cube, const tsa_region* region, double* d_out, void*
             tsa_stream_t stream);
 
 /*
- * Batched region queries ("local" statistics over user-defined regions,
+ * Batched region queries (local statistics over caller-chosen boxes,
  * Section 4; the statistical mini-map of Section 4.5 is a regular grid of
  * them).  For each of the nq boxes in d_regions (device array), computes what
  * tsa_stats computes, with the histogram over the box's own [min, max]:

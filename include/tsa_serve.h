@@ -3,8 +3,9 @@
  * (libtsa.so).
  *
  * The paper's framework answers analysis requests from remote clients against
- * cubes held in GPU memory ("move the question to the data", Sections 2 and
- * 5); this is that service on one GPU.  A server owns a scheduler thread that
+ * cubes held in GPU memory, so that requests travel to where the data sits
+ * instead of the data to the client (Sections 2 and 5); this is that service
+ * on one GPU.  A server owns a scheduler thread that
  *   - keeps a registry of resident cubes (min/max computed when a cube is
  *     added, as Section 4.1 computes them while the data loads);
  *   - admits requests while a device-scratch budget and a slot limit allow;
