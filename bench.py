@@ -411,6 +411,7 @@ def _region_batch_bench(tsa, torch, np, synth, reps: int) -> dict:
             "status_errors": bad, "phase3_queries": phase3, "generate_s": round(t_gen, 1),
             "untuned_ms": round(default_ms, 3), "tuned": {"tile_voxels": best[0], "block_threads": best[1],
                                                           "blocks_per_cu": best[2], "cand_max": best[3],
+                                                          "replicas": best[4],
                                                           "tuner_best_ms": round(best_ms, 3),
                                                           "tuning_s": round(t_tune, 1)}}
 

@@ -100,7 +100,10 @@ typedef enum {
 
 /* Tunables of tsa_region_batch (NULL = the autotuner's remembered choice for
  * the batch's shape, else the defaults: automatic tiles, 4 blocks per CU,
- * 2^20-key candidate cap). */
+ * 2^20-key candidate cap, replicas by bin count).  In a given struct,
+ * tile_voxels below 1024, blocks_per_cu 0 and replicas 0 keep their defaults;
+ * cand_max is taken as given (0: no candidate copy, every box whose median
+ * needs a last digit takes a third pass). */
 typedef struct {
   int32_t tile_voxels;     /* target voxels per work item (>= 1024); below 1024: chosen on the
                               device so the batch makes about four tiles per persistent block,
@@ -108,6 +111,9 @@ typedef struct {
   int32_t block_threads;   /* 0 or 256 (the batch kernel's block size; others: TSA_ENOTSUP) */
   int32_t blocks_per_cu;   /* persistent blocks per compute unit, >= 1 */
   int32_t cand_max;        /* largest bucket compacted for the median's last digits */
+  int32_t replicas;        /* LDS copies of each histogram bin (bin privatisation): 1, 2, 4 or 8;
+                              0 = by bin count (4 up to 1024 bins, 2 up to 2048, else 1); fewer
+                              are used where the copies would not fit the block's LDS */
 } tsa_tune;
 
 /*
@@ -238,9 +244,12 @@ int tsa_region_batch(const tsa_cube* cube, const tsa_region* d_regions, int32_t 
 
 /*
  * Autotuner of tsa_region_batch: runs the caller's batch (same arguments as
- * tsa_region_batch; outputs are overwritten) under a grid of launch choices
- * (tile size x persistent blocks per compute unit), `reps` timed runs each
- * after one warm-up, and writes the fastest to *best (and its mean time in
+ * tsa_region_batch; outputs are overwritten) under a search over launch
+ * choices -- tile size (automatic, 64K, 256K, 1M voxels) x persistent blocks
+ * per compute unit (2, 4, 6, 8), then LDS replicas per histogram bin (1, 2,
+ * 4, 8) at the best of those, then the candidate cap (64K, 256K, 1M, 4M keys)
+ * -- `reps` timed runs each after one warm-up, and writes the fastest to *best
+ * (and its mean time in
  * milliseconds to *best_ms, if not NULL).  The choice is remembered for the
  * batch's shape class (device architecture, dtype, nbins, log2 nq) and used by
  * later tsa_region_batch calls with tune == NULL.  Synchronizes the stream.

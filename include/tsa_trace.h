@@ -64,6 +64,16 @@ int32_t tsa_internal_probe_blocks(void);
  */
 int tsa_internal_batch_wait_limit(int32_t polls);
 
+/*
+ * Testing support: the launch choices of the last region batch this thread
+ * enqueued (a graph replay enqueues nothing): out[0] = tile units requested
+ * (0: chosen on the device), out[1] = persistent blocks per compute unit,
+ * out[2] = LDS replicas per histogram bin, out[3] = candidate cap.  out is a
+ * host array of 4 ints.  Returns TSA_EINVAL for NULL, TSA_ENOTSUP before the
+ * thread's first batch, else TSA_OK.
+ */
+int tsa_internal_batch_last_config(int32_t* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -48,7 +48,7 @@ class Region(ctypes.Structure):
 
 class Tune(ctypes.Structure):
     _fields_ = [("tile_voxels", ctypes.c_int32), ("block_threads", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32), ("cand_max", ctypes.c_int32)]
+                ("blocks_per_cu", ctypes.c_int32), ("cand_max", ctypes.c_int32), ("replicas", ctypes.c_int32)]
 
 
 # tsa_result as a numpy record (72 bytes)
@@ -317,8 +317,8 @@ def region_batch(t, regions, nbins: int, tune: Optional[Sequence[int]] = None, s
 
 def tune_region_batch(t, regions, nbins: int, reps: int = 3, stream=None):
     """Run the autotuner on this batch; returns ((tile_voxels, block_threads,
-    blocks_per_cu, cand_max), best ms).  Later region_batch calls of the same
-    shape class use the choice when no tune is given."""
+    blocks_per_cu, cand_max, replicas), best ms).  Later region_batch calls of
+    the same shape class use the choice when no tune is given."""
     torch = _torch()
     c = cube_of(t)
     reg = torch.as_tensor(regions, dtype=torch.int64).to(t.device).contiguous()
@@ -331,7 +331,15 @@ def tune_region_batch(t, regions, nbins: int, reps: int = 3, stream=None):
     _check(capi().tsa_tune_region_batch(ctypes.byref(c), reg.data_ptr(), nq, nbins, out.data_ptr(), hists.data_ptr(),
                                         ws.data_ptr(), ws.numel(), _stream(stream), reps, ctypes.byref(best),
                                         ctypes.byref(ms)), "tsa_tune_region_batch")
-    return (best.tile_voxels, best.block_threads, best.blocks_per_cu, best.cand_max), ms.value
+    return (best.tile_voxels, best.block_threads, best.blocks_per_cu, best.cand_max, best.replicas), ms.value
+
+
+def batch_last_config():
+    """(tile units requested, blocks per CU, LDS replicas per bin, candidate
+    cap) of the last region batch this thread enqueued (testing support)."""
+    out = (ctypes.c_int32 * 4)()
+    _check(capi().lib.tsa_internal_batch_last_config(out), "tsa_internal_batch_last_config")
+    return tuple(out)
 
 
 def minimap(t, cell: Sequence[int], nbins: int, stream=None, ws=None):

@@ -9,7 +9,11 @@
 //                     + second moment about the mean) of tile t - T1
 //   t in [2 T1, 3 T1) phase 3 (rare): last key digit of tile t - 2 T1
 // The block that finishes the last tile of a box's phase runs that box's
-// epilogue (merge, digit selection, next-phase set-up).  A phase-2 tile waits
+// epilogue (merge, digit selection, next-phase set-up).  A box that is one
+// tile ("solo") is finished whole by the block that draws its phase-1 ticket:
+// both passes (and the rare third) back to back, its counters kept in that
+// block's LDS, no other block involved and nothing to publish; its phase-2
+// and phase-3 tickets are skipped.  A phase-2 tile waits
 // for its box's phase-1 epilogue; a phase-3 tile skips at once unless phase 1
 // left its box without a candidate copy, and then waits for the box's phase-2
 // epilogue.  Tickets are handed out in increasing order, so every wait is on
@@ -41,6 +45,7 @@ struct QGeom {
   int64_t v_origin;
   uint64_t volume;
   uint32_t ly, nrows, vpr, rpt, ntiles, head_skip, last_valid, valid;
+  uint32_t solo;  // one tile: the whole box in one block
   Magic ly_m, vpr_m;
 };
 
@@ -56,9 +61,23 @@ struct QState {
 struct BatchHdr {
   uint64_t T1;
   uint64_t ticket;
-  uint32_t pool_top, err;
+  // keys of the candidate pool handed out, or asked for past its end: a 64-bit
+  // sum of at most 65536 buckets below 2^32 each never wraps
+  uint64_t pool_top;
+  uint32_t err;
   uint32_t nq, tile_units;  // tile_units: chosen on the device when the caller set none
 };
+
+// Reserves `bucket` keys of the shared candidate pool with one atomic add
+// (a compare-and-swap loop costs microseconds per success when a thousand
+// blocks contend).  Returns false, leaving the range to nobody, when the
+// pool has no room; the counter then only grows past pool_keys.
+TSA_DEV bool pool_reserve(BatchHdr* hdr, uint32_t bucket, uint32_t pool_keys, uint32_t* base) {
+  const uint64_t b = atomicAdd((unsigned long long*)&hdr->pool_top, (unsigned long long)bucket);
+  if (b + bucket > pool_keys) return false;
+  *base = (uint32_t)b;
+  return true;
+}
 
 struct BArgs {
   const void* base;
@@ -173,6 +192,7 @@ __global__ void k_bplan(BArgs a) {
       g.ly_m = dev_magic(g.ly);
       g.vpr_m = dev_magic(g.vpr);
       g.valid = ok ? 1u : 0u;
+      g.solo = (ok && nt == 1) ? 1u : 0u;
       res.nan_count = vol;  // until the moments say otherwise
     }
   }
@@ -233,6 +253,8 @@ __global__ __launch_bounds__(1024) void k_bscan(BArgs a) {
 struct BShared {
   uint64_t t;
   uint32_t q, tile, last, flag;
+  uint32_t cand_base, compact;
+  Partial part;
   MomShared mom;
   uint32_t wsum32[16];
   uint32_t found, sel_digit, sel_cum32, sel_bucket32;
@@ -410,21 +432,12 @@ TSA_DEV void epilogue1(const BArgs& a, uint32_t q, BShared& sh, uint32_t* lds) {
         s.shift = s.var_on ? (float)mean : 0.0f;
         s.compact = 0;
         // int16 keys are complete after the second digit: no candidates needed.
-        // The pool counter only advances while the reservation fits (pool_keys
-        // <= 2^28 and a bucket <= cand_max < 2^31, so the sum never wraps): a
-        // box that finds the pool full takes the third pass instead.
-        if (DT == 0 && bucket <= a.cand_max) {
-          uint32_t cur = __hip_atomic_load(&a.hdr->pool_top, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          while ((uint64_t)cur + bucket <= a.pool_keys) {
-            const uint32_t seen = atomicCAS(&a.hdr->pool_top, cur, cur + (uint32_t)bucket);
-            if (seen == cur) {
-              s.compact = 1;
-              s.cand_base = cur;
-              s.cand_n = (uint32_t)bucket;
-              break;
-            }
-            cur = seen;
-          }
+        // A box that finds the pool full takes the third pass instead.
+        uint32_t base = 0;
+        if (DT == 0 && bucket <= a.cand_max && pool_reserve(a.hdr, bucket, a.pool_keys, &base)) {
+          s.compact = 1;
+          s.cand_base = base;
+          s.cand_n = (uint32_t)bucket;
         }
       }
     }
@@ -576,6 +589,176 @@ TSA_DEV void walk_tile(const BArgs& a, const QGeom& g, uint32_t tile, F& f) {
 }
 
 // ---------------------------------------------------------------------------
+// a one-tile box, whole, in one block (phase-1 ticket of a solo box)
+// ---------------------------------------------------------------------------
+// The same steps and arithmetic as the tiled path -- the partial, the merge of
+// one partial, the digit choices, the histogram formula, the candidate pool
+// -- so the results are the same bits; only the counters stay in LDS between
+// the passes instead of going through global memory and the epilogues.
+template <int DT, bool VEC, bool NT, class CS>
+TSA_DEV void solo_box(const BArgs& a, uint32_t q, BShared& sh, CS& cs, uint32_t* lds) {
+  const QGeom& g = a.geom[q];
+  QState& s = a.st[q];
+  tsa_result& R = a.results[q];
+  const int t = threadIdx.x;
+  // pass 1: moments + first key digit
+  lds_zero(lds, kBins1 + kTrash);
+  __syncthreads();
+  BPass1<DT> f{MomAcc<DT, false>{}, Digit1Acc<DT>{lds, 0u, 0u}};
+  walk_tile<DT, VEC, NT>(a, g, 0u, f);
+  __syncthreads();
+  uint32_t c = 0;  // every valid value incremented one first-digit counter
+  for (int b = t; b < kBins1; b += kBBlock) c += lds[b];
+  f.mom.cnt = c;
+  block_store_partial(f.mom, sh.mom, &sh.part);
+  __syncthreads();
+  const Partial p = sh.part;
+  double n = 0.0, mean = 0.0, m2 = 0.0;
+  partial_stats(p, DT, n, mean, m2);
+  const uint64_t cnt = p.n;
+  const uint32_t kmin = cnt ? p.kmin : 0xFFFFFFFFu, kmax = cnt ? p.kmax : 0u;
+  const double vmin = bvalue_of_key(kmin, DT), vmax = bvalue_of_key(kmax, DT);
+  if (t == 0) {
+    R.count = cnt;
+    R.nan_count = g.volume - cnt;
+    s.n = cnt;
+    if (cnt == 0) {
+      R.flags |= TSA_FLAG_HIST_SKIPPED;
+    } else {
+      R.min = vmin;
+      R.max = vmax;
+      if (kmin == kmax) {
+        R.mean = vmin;
+        R.m2 = 0.0;
+        R.std = 0.0;
+        R.median = vmin;
+        if (isfinite((float)vmin))
+          a.hists[(size_t)q * a.nbins] = cnt;  // lo == hi: every value in bin 0
+        else
+          R.flags |= TSA_FLAG_HIST_SKIPPED;  // an infinite range has no bins
+      } else {
+        const double q2 = m2 < 0.0 ? 0.0 : m2;  // NaN (infinite values) stays
+        R.mean = mean;
+        R.m2 = q2;
+        R.std = sqrt(q2 / (double)cnt);
+      }
+    }
+  }
+  if (cnt == 0 || kmin == kmax) {
+    if (t == 0) s.finished = 1;
+    return;
+  }
+  const uint32_t k = (uint32_t)((cnt - 1) / 2);  // a box holds fewer than 2^32 voxels
+  uint32_t d, cum, bucket;
+  if (!block_select_small(lds, kBins1, k, sh, &d, &cum, &bucket)) {
+    if (t == 0) {
+      R.status = TSA_EDEVICE;
+      s.finished = 1;
+    }
+    return;
+  }
+  const uint32_t prefix = d << kShift1;
+  const uint32_t k2 = k - cum;
+  // the histogram's range and scale, the shift of the second moment (every
+  // thread computes the same values)
+  const float lo = (float)vmin, hi = (float)vmax;
+  float scale = 0.f;
+  bool hist_on = false;
+  if (isfinite(lo) && isfinite(hi)) {
+    const float width = hi - lo;
+    if (isfinite(width)) {
+      scale = (float)a.nbins / width;
+      hist_on = isfinite(scale) && scale != 0.0f;
+    }
+  }
+  const double q2 = m2 < 0.0 ? 0.0 : m2;
+  const bool var_on = DT == 0 && isfinite(mean) && one_pass_m2_at_risk(mean, q2 / (double)cnt);
+  const float shift = var_on ? (float)mean : 0.0f;
+  if (t == 0) {
+    if (!hist_on) R.flags |= TSA_FLAG_HIST_SKIPPED;
+    // candidate pool reservation, as the tiled path makes it
+    uint32_t base = 0;
+    const uint32_t compact =
+        (DT == 0 && bucket <= a.cand_max && pool_reserve(a.hdr, bucket, a.pool_keys, &base)) ? 1u : 0u;
+    sh.compact = compact;
+    sh.cand_base = base;
+  }
+  __syncthreads();
+  const bool compact = sh.compact != 0;
+  const uint32_t cand_base = sh.cand_base;
+  // pass 2: histogram + second key digit (+ candidate copy, + second moment about the shift)
+  const uint32_t hsize = ((uint32_t)a.nbins << a.rshift) + kTrash;
+  uint32_t* l2 = lds + hsize;
+  lds_zero(lds, hsize + kBins2);
+  __syncthreads();
+  BPass2<DT> f2{HistOwnAcc{lds, lo, scale, a.nbins - 1, a.rshift, (uint32_t)t & ((1u << a.rshift) - 1u)},
+                Level2Acc<DT>{l2, prefix >> kShift1, compact, cand_sink(cs, a.pool + cand_base, &s.cand_fill, bucket)},
+                VarAcc{shift}, hist_on, var_on};
+  walk_tile<DT, VEC, NT>(a, g, 0u, f2);
+  f2.l2.finish();
+  __syncthreads();
+  if (hist_on) lds_flush(lds, (uint32_t)a.nbins, a.rshift, a.hists + (size_t)q * a.nbins);
+  if (var_on) {
+    const double vq = wave_sum_f64(f2.var.q);
+    const int w = t / kWave, lane = t % kWave;
+    if (lane == 0) sh.mom.q[w] = vq;
+    __syncthreads();
+    if (t == 0) {
+      double bq = sh.mom.q[0];
+      for (int i = 1; i < kBBlock / kWave; ++i) bq += sh.mom.q[i];
+      const double dm = R.mean - (double)shift;
+      double v = bq - (double)cnt * dm * dm;
+      if (v < 0.0) v = 0.0;  // rounding below zero; NaN (infinite values) stays
+      R.m2 = v;
+      R.std = sqrt(v / (double)cnt);
+    }
+  }
+  uint32_t d2, cum2, b2;
+  if (!block_select_small(l2, kBins2, k2, sh, &d2, &cum2, &b2)) {  // ends with a barrier
+    if (t == 0) {
+      R.status = TSA_EDEVICE;
+      s.finished = 1;
+    }
+    return;
+  }
+  const uint32_t prefix2 = prefix | (d2 << kShift2);
+  const uint32_t k3 = k2 - cum2;
+  if (DT == 1) {  // int16 keys have no bits below the second digit
+    if (t == 0) {
+      R.median = bvalue_of_key(prefix2, DT);
+      s.finished = 1;
+    }
+    return;
+  }
+  // last 8 bits: from the copied candidates, else a third pass over the box
+  for (int i = t; i < kBins3; i += kBBlock) lds[i] = 0u;
+  __syncthreads();
+  if (compact) {
+    const uint32_t* cl = a.pool + cand_base;
+    const uint32_t nc = min(bucket, __hip_atomic_load(&s.cand_fill, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    const uint32_t p2 = prefix2 >> kShift2;
+    for (uint32_t i = t; i < nc; i += kBBlock) {
+      const uint32_t key = cl[i];
+      if ((key >> kShift2) == p2) lds_inc(lds, key & 0xFFu);
+    }
+  } else {
+    Level3Acc<DT> f3{lds, prefix2 >> kShift2};
+    walk_tile<DT, VEC, NT>(a, g, 0u, f3);
+    if (t == 0) R.flags |= TSA_FLAG_PHASE3;
+  }
+  __syncthreads();
+  uint32_t d3, cum3, b3;
+  const bool found = block_select_small(lds, kBins3, k3, sh, &d3, &cum3, &b3);
+  if (t == 0) {
+    if (found)
+      R.median = bvalue_of_key(prefix2 | d3, DT);
+    else
+      R.status = TSA_EDEVICE;
+    s.finished = 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // the persistent kernel
 // ---------------------------------------------------------------------------
 template <int DT, bool VEC, bool NT>
@@ -616,6 +799,11 @@ __global__ __launch_bounds__(kBBlock) void k_batch(BArgs a) {
     const QGeom& g = a.geom[q];
     QState& s = a.st[q];
 
+    if (g.solo) {  // uniform across the block (every thread read the same q)
+      if (phase == 1) solo_box<DT, VEC, NT>(a, q, sh, cs, lds);
+      __syncthreads();
+      continue;  // its other tickets have nothing to do
+    }
     if (phase == 1) {
       lds_zero(lds, kBins1 + kTrash);
       __syncthreads();
@@ -774,6 +962,27 @@ size_t batch_ws_bytes(const tsa_cube* cube, int32_t nbins, int32_t nq) {
 
 static void bfill(void* p, size_t words, hipStream_t s);
 
+// launch choices of this thread's last enqueued batch (tsa_internal_batch_last_config)
+struct BatchConfig {
+  int32_t tile_units, bpc, replicas, cand_max;
+  bool set;
+};
+static thread_local BatchConfig g_last_config = {0, 0, 0, 0, false};
+
+// log2 of the LDS replicas per histogram bin of phase 2: the caller's choice
+// (0: 4 up to 1024 bins, 2 up to 2048, else 1), reduced while the phase-2
+// counters (replicated bins + second-digit bins) would not fit one launch's
+// 64 KB or the block's share of the compute unit's LDS.
+uint32_t batch_rep_shift(int32_t nbins, int replicas, size_t lds_per_cu, int bpc) {
+  uint32_t r = replicas == 0 ? (nbins <= 1024 ? 2u : nbins <= 2048 ? 1u : 0u)
+                             : (uint32_t)__builtin_ctz((unsigned)replicas);
+  size_t cap = lds_per_cu / (size_t)(bpc > 0 ? bpc : 1);
+  if (cap > 65536) cap = 65536;
+  cap = cap > 2048 ? cap - 2048 : 0;  // the kernel's static LDS
+  while (r > 0 && ((((size_t)nbins << r) + kTrash + kBins2) * 4) > cap) --r;
+  return r;
+}
+
 static int enqueue_region_batch(const tsa_cube* cube, const tsa_region* d_regions, int32_t nq, int32_t nbins,
                                 tsa_result* d_results, uint64_t* d_hists, const tsa_tune* tune, void* d_ws,
                                 size_t ws_bytes, hipStream_t s);
@@ -919,6 +1128,7 @@ int run_region_batch(const tsa_cube* cube, const tsa_region* d_regions, int32_t 
     key.v[14] = ((uintptr_t)(uint32_t)tune->tile_voxels << 32) | (uint32_t)tune->block_threads;
     key.v[15] = ((uintptr_t)(uint32_t)tune->blocks_per_cu << 32) | (uint32_t)tune->cand_max;
     key.v[16] = 1;
+    key.v[17] = (uintptr_t)(uint32_t)tune->replicas;
   }
   BatchCall c{cube, d_regions, nq, nbins, d_results, d_hists, tune, d_ws, ws_bytes};
   return graph_run(key, s, enqueue_batch_call, &c);
@@ -937,11 +1147,16 @@ static int enqueue_region_batch(const tsa_cube* cube, const tsa_region* d_region
   if ((st = device_info(&dev))) return st;
   uint32_t tile_units = 0, cand_max = kBatchCandMax;  // 0: chosen on the device from the batch's volume
   int bpc = 4;
+  int replicas = 0;  // 0: by bin count
   if (tune) {
     if (tune->tile_voxels >= 1024) tile_units = (uint32_t)tune->tile_voxels / (cube->dtype == TSA_F32 ? 4 : 8);
     if (tune->blocks_per_cu >= 1 && tune->blocks_per_cu <= 16) bpc = tune->blocks_per_cu;
     if (tune->cand_max >= 0) cand_max = (uint32_t)tune->cand_max;
     if (tune->block_threads != 0 && tune->block_threads != kBBlock) return TSA_ENOTSUP;
+    if (tune->replicas != 0 && tune->replicas != 1 && tune->replicas != 2 && tune->replicas != 4 &&
+        tune->replicas != 8)
+      return TSA_EINVAL;
+    replicas = tune->replicas;
   }
   if (tile_units && tile_units < 256) tile_units = 256;
   const int epv = cube->dtype == TSA_F32 ? 4 : 8;
@@ -956,7 +1171,8 @@ static int enqueue_region_batch(const tsa_cube* cube, const tsa_region* d_region
   a.regions = d_regions;
   a.nq = nq;
   a.nbins = nbins;
-  a.rshift = nbins <= 1024 ? 2u : nbins <= 2048 ? 1u : 0u;
+  a.rshift = batch_rep_shift(nbins, replicas, dev.lds_per_block, bpc);
+  g_last_config = BatchConfig{(int32_t)tile_units, bpc, 1 << a.rshift, (int32_t)cand_max, true};
   a.tile_units = tile_units;
   a.grid = (uint32_t)(dev.cus * bpc);
   {
@@ -1026,6 +1242,17 @@ static void bfill(void* p, size_t words, hipStream_t s) {
 }
 
 }  // namespace tsa
+
+extern "C" int tsa_internal_batch_last_config(int32_t* out) {
+  if (!out) return TSA_EINVAL;
+  const tsa::BatchConfig& c = tsa::g_last_config;
+  if (!c.set) return TSA_ENOTSUP;
+  out[0] = c.tile_units;
+  out[1] = c.bpc;
+  out[2] = c.replicas;
+  out[3] = c.cand_max;
+  return TSA_OK;
+}
 
 extern "C" int tsa_internal_batch_wait_limit(int32_t polls) {
   tsa::g_wait_polls.store(polls < 0 ? -1 : (int64_t)polls);

@@ -74,34 +74,42 @@ int tsa_tune_region_batch(const tsa_cube* cube, const tsa_region* d_regions, int
     (void)hipEventDestroy(e0);
     return TSA_EDEVICE;
   }
-  const int32_t tiles[] = {65536, 262144, 1048576};
-  const int32_t bpcs[] = {2, 4, 6, 8};
+  // coordinate search: tile size x blocks per CU, then the LDS replicas of
+  // each histogram bin at the best of those, then the candidate cap
   float bms = 1e30f;
   const int32_t cm = (int32_t)kBatchCandMax;
-  tsa_tune bt = {65536, 256, 4, cm};
-  for (int32_t tv : tiles) {
-    for (int32_t bpc : bpcs) {
-      tsa_tune t = {tv, 256, bpc, cm};
-      st = run_region_batch(cube, d_regions, nq, nbins, d_results, d_hists, &t, d_ws, ws_bytes, stream);  // warm
-      if (st) break;
-      (void)hipEventRecord(e0, s);
-      for (int r = 0; r < reps && st == TSA_OK; ++r)
-        st = run_region_batch(cube, d_regions, nq, nbins, d_results, d_hists, &t, d_ws, ws_bytes, stream);
-      (void)hipEventRecord(e1, s);
-      if (st || hipEventSynchronize(e1) != hipSuccess) {
-        st = st ? st : TSA_EDEVICE;
-        break;
-      }
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      ms /= (float)reps;
-      if (ms < bms) {
-        bms = ms;
-        bt = t;
-      }
+  tsa_tune bt = {0, 256, 4, cm, 0};
+  auto trial = [&](const tsa_tune& t) -> int {
+    int r = run_region_batch(cube, d_regions, nq, nbins, d_results, d_hists, &t, d_ws, ws_bytes, stream);  // warm
+    if (r) return r;
+    (void)hipEventRecord(e0, s);
+    for (int i = 0; i < reps && r == TSA_OK; ++i)
+      r = run_region_batch(cube, d_regions, nq, nbins, d_results, d_hists, &t, d_ws, ws_bytes, stream);
+    (void)hipEventRecord(e1, s);
+    if (r) return r;
+    if (hipEventSynchronize(e1) != hipSuccess) return TSA_EDEVICE;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    ms /= (float)reps;
+    if (ms < bms) {
+      bms = ms;
+      bt = t;
     }
-    if (st) break;
-  }
+    return TSA_OK;
+  };
+  const int32_t tiles[] = {0, 65536, 262144, 1048576};
+  const int32_t bpcs[] = {2, 4, 6, 8};
+  for (int32_t tv : tiles)
+    for (int32_t bpc : bpcs)
+      if (!st) st = trial(tsa_tune{tv, 256, bpc, cm, 0});
+  const int32_t reps_of_bin[] = {1, 2, 4, 8};
+  const tsa_tune b1 = bt;
+  for (int32_t r : reps_of_bin)
+    if (!st) st = trial(tsa_tune{b1.tile_voxels, 256, b1.blocks_per_cu, cm, r});
+  const int32_t caps[] = {65536, 262144, 4 << 20};  // 1M was measured with every choice above
+  const tsa_tune b2 = bt;
+  for (int32_t c : caps)
+    if (!st) st = trial(tsa_tune{b2.tile_voxels, 256, b2.blocks_per_cu, c, b2.replicas});
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st) return st;
@@ -120,8 +128,8 @@ int tsa_tune_save(const char* path) {
   fprintf(f, "{");
   bool first = true;
   for (auto& kv : table()) {
-    fprintf(f, "%s\n  \"%s\": [%d, %d, %d, %d]", first ? "" : ",", kv.first.c_str(), kv.second.tile_voxels,
-            kv.second.block_threads, kv.second.blocks_per_cu, kv.second.cand_max);
+    fprintf(f, "%s\n  \"%s\": [%d, %d, %d, %d, %d]", first ? "" : ",", kv.first.c_str(), kv.second.tile_voxels,
+            kv.second.block_threads, kv.second.blocks_per_cu, kv.second.cand_max, kv.second.replicas);
     first = false;
   }
   fprintf(f, "\n}\n");
@@ -138,7 +146,7 @@ int tsa_tune_load(const char* path) {
   size_t n;
   while ((n = fread(buf, 1, sizeof(buf), f)) > 0) txt.append(buf, n);
   fclose(f);
-  // entries: "key": [a, b, c, d]
+  // entries: "key": [tile_voxels, block_threads, blocks_per_cu, cand_max(, replicas)]
   int loaded = 0;
   size_t pos = 0;
   std::lock_guard<std::mutex> g(g_mu);
@@ -150,8 +158,10 @@ int tsa_tune_load(const char* path) {
     const size_t lb = txt.find('[', q1), rb = txt.find(']', q1);
     if (lb == std::string::npos || rb == std::string::npos || rb < lb) break;
     tsa_tune t;
-    if (sscanf(txt.c_str() + lb + 1, "%d , %d , %d , %d", &t.tile_voxels, &t.block_threads, &t.blocks_per_cu,
-               &t.cand_max) == 4) {
+    t.replicas = 0;  // entries written before the replica count was tuned hold four numbers
+    const int got = sscanf(txt.c_str() + lb + 1, "%d , %d , %d , %d , %d", &t.tile_voxels, &t.block_threads,
+                           &t.blocks_per_cu, &t.cand_max, &t.replicas);
+    if (got == 4 || got == 5) {
       table()[txt.substr(q0 + 1, q1 - q0 - 1)] = t;
       ++loaded;
     }

@@ -116,14 +116,15 @@ def test_batch_workspace_bytes():
 def test_tune_cache_roundtrip(tmp_path):
     c = tsa.capi()
     p = tmp_path / "tune.json"
+    # entries of four numbers (written before the replica count was tuned) load with replicas 0
     p.write_text('{\n  "gfx950|f32|nbins=256|nq2=12": [65536, 256, 4, 65536],\n'
-                 '  "gfx950|i16|nbins=128|nq2=3": [16384, 256, 8, 0]\n}\n')
+                 '  "gfx950|i16|nbins=128|nq2=3": [16384, 256, 8, 0, 2]\n}\n')
     assert c.tsa_tune_load(str(p).encode()) == 2
     q = tmp_path / "out.json"
     assert c.tsa_tune_save(str(q).encode()) == 0
     txt = q.read_text()
-    assert '"gfx950|f32|nbins=256|nq2=12": [65536, 256, 4, 65536]' in txt
-    assert '"gfx950|i16|nbins=128|nq2=3": [16384, 256, 8, 0]' in txt
+    assert '"gfx950|f32|nbins=256|nq2=12": [65536, 256, 4, 65536, 0]' in txt
+    assert '"gfx950|i16|nbins=128|nq2=3": [16384, 256, 8, 0, 2]' in txt
     assert c.tsa_tune_load(str(tmp_path / "missing.json").encode()) == tsa.TSA_EINVAL
 
 

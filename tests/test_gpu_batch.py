@@ -192,8 +192,47 @@ def test_autotuner_choice_is_used_and_correct():
     boxes = _boxes((128, 96, 64), 123, 31, lo=4, hi=96)
     _say("case batch autotuner")
     best, ms = tsa.tune_region_batch(dev, boxes, 64, reps=1)
-    assert best[0] in (65536, 262144, 1048576) and best[2] in (2, 4, 6, 8) and ms > 0
-    _check_batch(host, dev, boxes, 64, what="tuned")  # tune=None: the remembered choice
+    assert best[0] in (0, 65536, 262144, 1048576) and best[2] in (2, 4, 6, 8) and ms > 0
+    assert best[3] in (65536, 262144, 1 << 20, 4 << 20) and best[4] in (0, 1, 2, 4, 8)
+    # with tracing on, calls launch directly (no graph replay), so the launch
+    # choices recorded are this call's: the remembered ones
+    lib = tsa.capi().lib
+    lib.tsa_trace_enable.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    assert lib.tsa_trace_enable(1, 64) == 0
+    try:
+        res, hists = _check_batch(host, dev, boxes, 64, what="tuned")  # tune=None: the remembered choice
+        tiles, bpc, reps, cap = tsa.batch_last_config()
+    finally:
+        lib.tsa_trace_enable(0, 0)
+    assert bpc == best[2] and cap == best[3], (best, tsa.batch_last_config())
+    assert tiles == (best[0] // 4 if best[0] >= 1024 else 0)
+    assert reps == (best[4] if best[4] else 4)  # 64 bins: 4 replicas by default
+    # every replica count gives the same bits
+    for r in (1, 2, 4, 8):
+        got, gh = tsa.region_batch(dev, boxes, 64, tune=(best[0], 256, 4, best[3], r))
+        assert got.tobytes() == res.tobytes() and np.array_equal(gh.cpu().numpy().view(np.uint64), hists), r
+
+
+def test_replicas_reduced_to_fit_lds():
+    """4096 bins x 8 replicas would not fit a block's LDS: the batch uses as
+    many as fit (here one) and stays exact."""
+    spec = synth.scaled(synth.SPECS["c1"], 64, 64, 32)
+    host, _ = synth.generate(spec)
+    dev = _dev(host)
+    boxes = _boxes((64, 64, 32), 20, 7, lo=4, hi=48)
+    _say("case batch replicas 8 at 4096 bins")
+    lib = tsa.capi().lib
+    lib.tsa_trace_enable.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    assert lib.tsa_trace_enable(1, 64) == 0  # direct launches: the recorded choices are this call's
+    try:
+        _check_batch(host, dev, boxes, 4096, tune=(0, 256, 4, 1 << 20, 8), what="replicas 8")
+        assert tsa.batch_last_config()[2] == 1
+        _check_batch(host, dev, boxes, 256, tune=(0, 256, 4, 1 << 20, 8), what="replicas 8, 256 bins")
+        assert tsa.batch_last_config()[2] == 8
+    finally:
+        lib.tsa_trace_enable(0, 0)
+    with pytest.raises(tsa.TsaError):
+        tsa.region_batch(dev, boxes, 64, tune=(0, 256, 4, 1 << 20, 3))
 
 
 def test_batch_candidate_pool_fills_without_wrapping():
@@ -228,12 +267,23 @@ def test_batch_candidate_pool_fills_without_wrapping():
         check_hist(hists[i], None, counts[i], None, f"pool q{i}")
 
 
+def _solo(box, tile_voxels):
+    """True when the batch plans the box as one tile (float32, 16-byte rows):
+    tile_voxels / 4 vectors per tile, whole rows of ceil(x1/4) - floor(x0/4)
+    vectors each."""
+    x0, y0, z0, x1, y1, z1 = (int(v) for v in box)
+    vpr = -(-x1 // 4) - x0 // 4
+    rpt = max(1, (tile_voxels // 4) // vpr)
+    return (y1 - y0) * (z1 - z0) <= rpt
+
+
 def test_batch_bounded_wait_gives_up_cleanly():
     """The persistent kernel's bounded waits, forced from the host to give up
-    at their first poll: the kernel still exits, every box that needed its
-    second phase reports TSA_EDEVICE, boxes finished in their first phase
-    (constant or all-NaN boxes) keep their results, and the next batch on the
-    same workspace is correct again."""
+    at their first poll: the kernel still exits, every box of several tiles
+    that needed its second phase reports TSA_EDEVICE, boxes finished in their
+    first phase (constant or all-NaN boxes) and one-tile boxes (finished whole
+    by one block, no wait) keep their results, and the next batch on the same
+    workspace is correct again."""
     spec = synth.scaled(synth.SPECS["c1"], 96, 64, 48)
     host, _ = synth.generate(spec)
     host[:8, :8, :16] = np.float32(2.5)  # a constant corner
@@ -241,19 +291,22 @@ def test_batch_bounded_wait_gives_up_cleanly():
     boxes = _boxes((96, 64, 48), 60, seed=9, lo=2, hi=40)
     const_box = np.array([[0, 0, 0, 16, 8, 8], [0, 0, 40, 8, 4, 44]], dtype=np.int64)
     boxes = np.concatenate([boxes, const_box])
+    tile = 1024
+    solo = [_solo(b, tile) for b in boxes]
+    assert 5 < sum(solo) < len(boxes) - 5
     dev = _dev(host)
     lib = tsa.capi().lib
     lib.tsa_internal_batch_wait_limit.argtypes = [ctypes.c_int32]
     lib.tsa_internal_batch_wait_limit(0)
     try:
         _say("case wait limit 0")
-        res, _ = tsa.region_batch(dev, boxes, 32)
+        res, _ = tsa.region_batch(dev, boxes, 32, tune=(tile, 256, 4, 1 << 20, 0))
     finally:
         lib.tsa_internal_batch_wait_limit(-1)
     for i, b in enumerate(boxes):
         want = oracle.stats(host, 32, tuple(int(v) for v in b))
         r = {k: res[i][k].item() for k in res.dtype.names}
-        if want["count"] == 0 or np.float32(want["min"]).tobytes() == np.float32(want["max"]).tobytes():
+        if solo[i] or want["count"] == 0 or np.float32(want["min"]).tobytes() == np.float32(want["max"]).tobytes():
             assert r["status"] == 0, (i, b, r)
             check_moments(r, want, "f32", f"wait q{i}")
             check_median(r["median"], want["median"], "f32", f"wait q{i}")
