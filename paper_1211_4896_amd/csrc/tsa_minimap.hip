@@ -4,8 +4,10 @@
 // mean + k standard deviations.
 //
 // Cells of at most 32768 voxels (a 30x30x30 cell is 27000) are answered by one
-// 1024-lane workgroup each, the cell read from HBM once into registers (up to
-// 32 values per lane): moments and the first key digit, then the histogram
+// 512-lane workgroup each, the cell read from HBM once into registers (up to
+// 64 values per lane; at most ~100 registers a lane, so two workgroups share
+// a compute unit and one's loads and barriers overlap the other's counting):
+// moments and the first key digit, then the histogram
 // over the cell's own [min, max] and the other two radix digits of the median,
 // all from registers, with only the counters in LDS.  Larger cells go through
 // the region batch over the grid's boxes (planned on the device, so no box
@@ -247,7 +249,7 @@ __global__ __launch_bounds__(kSigBlock) void k_sigma(SigArgs a) {
 }
 
 // ---- LDS-resident cells ----------------------------------------------------------
-constexpr int kMMBlock = 1024;
+constexpr int kMMBlock = 512;
 
 struct MMArgs {
   const void* base;
@@ -273,9 +275,8 @@ struct MMShared {
   uint32_t status;
 };
 
-// One workgroup per cell, the cell held in registers: lane t keeps voxels
-// t + 1024 j (j < EPT) of the cell, so a 30^3 cell is 27 values per lane, all
-// loaded at once, and the LDS holds only counters.  The per-value work
+// One workgroup per cell, the cell held in registers (a 30^3 cell is 53
+// values per lane), all loaded at once, and the LDS holds only counters.  The per-value work
 // (moments, keys, digits, histogram) bounds this kernel by VALU issue, not
 // by HBM.  Every value is held as float32: int16 converts exactly, its double
 // sums stay exact (a cell's sums of squares stay below 2^53) and float keys
@@ -283,7 +284,16 @@ struct MMShared {
 // validity test is needed.  Block b works on cell (b % 8) * per_xcd + b / 8,
 // so the cells one XCD (and its L2) sees are neighbours sharing cache lines at
 // their x edges.
-template <int DT, int EPT>
+//
+// Two ways to spread a cell over the lanes.  PLANE (cells whose x*y face
+// holds at most 512 voxels, e.g. 16^3): lane t owns column t % w of row
+// (t / w) % h in z-slab t / (w h) of the face, P = 512 / (w h) slabs side by
+// side, and its values are that voxel in planes z, z + P, z + 2P, ...: one
+// constant address step, no per-value index arithmetic (lanes past P whole
+// faces hold NaN).  Otherwise lane t keeps voxels t + 512 j of the cell in
+// x-fastest order, stepping a (column, row, plane) cursor per value.
+// Value slots at or past the cell's own count ept_c skip every phase.
+template <int DT, int EPT, bool PLANE>
 __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
   using T = typename Ty<DT>::T;
   extern __shared__ uint32_t lds[];  // digit counters [kBins1 + kTrash] | histogram [(nbins << rshift) + kTrash]
@@ -305,14 +315,31 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
 
   // 1. every load of the lane in flight at once
   float x[EPT];
-  {
-    // voxel v = t + 1024 j of the cell is (v % w, (v / w) % h, v / (w h)); the
-    // lane divides once, then steps by 1024 voxels with constant increments
+  int ept_c;  // value slots that can hold a voxel of this cell (the same in every lane)
+  const int64_t plane = a.nx * a.ny;
+  const T* base = (const T*)a.base + (z0 * plane + y0 * a.nx + x0);
+  const Magic mw = w == (uint32_t)a.cx ? a.mx_full : a.mx_edge;
+  const Magic mh = h == (uint32_t)a.cy ? a.my_full : a.my_edge;
+  if constexpr (PLANE) {
+    const uint32_t P = (uint32_t)kMMBlock / (w * h);  // >= 1: checked on the host for the full face
+    ept_c = (int)((dd + P - 1) / P);
+    const uint32_t row = mdiv((uint32_t)t, mw);
+    const uint32_t lx = (uint32_t)t - row * w, lz = mdiv(row, mh), ly = row - lz * h;
+    const T* p = base + ((int64_t)lz * plane + (int64_t)ly * a.nx + lx);
+    const int64_t step = (int64_t)P * plane;
+    const bool lane_in = lz < P;  // lanes past the P whole faces hold nothing
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      if (lane_in && lz + (uint32_t)j * P < dd)  // planes past the cell never touch memory
+        x[j] = (float)p[j * step];
+      else
+        x[j] = __builtin_nanf("");
+    }
+  } else {
+    // voxel v = t + 512 j of the cell is (v % w, (v / w) % h, v / (w h)); the
+    // lane divides once, then steps by 512 voxels with constant increments
     // and at most one carry per axis (no division in the loop)
-    const int64_t plane = a.nx * a.ny;
-    const T* base = (const T*)a.base + (z0 * plane + y0 * a.nx + x0);
-    const Magic mw = w == (uint32_t)a.cx ? a.mx_full : a.mx_edge;
-    const Magic mh = h == (uint32_t)a.cy ? a.my_full : a.my_edge;
+    ept_c = (int)((nvox + kMMBlock - 1) / kMMBlock);
     const uint32_t dq = mdiv((uint32_t)kMMBlock, mw), dr = (uint32_t)kMMBlock - dq * w;
     const uint32_t dqz = mdiv(dq, mh), dqy = dq - dqz * h;
     const int64_t dstep = (int64_t)dqz * plane + (int64_t)dqy * a.nx + dr;
@@ -347,8 +374,10 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
   MomAcc<0, false> mom;  // the count is the first-digit histogram's total
 #pragma unroll
   for (int j = 0; j < EPT; ++j) {
-    mom(x[j], true);
-    if (x[j] == x[j]) lds_inc(dig, key_f32(__float_as_uint(x[j])) >> kShift1);
+    if (j < ept_c) {  // uniform
+      mom(x[j], true);
+      if (x[j] == x[j]) lds_inc(dig, key_f32(__float_as_uint(x[j])) >> kShift1);
+    }
   }
   __syncthreads();
   {
@@ -424,10 +453,12 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
     const bool hist_on = sh.hist_ok != 0, var_on = sh.var_on != 0;
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
-      if (hist_on) hacc(x[j], true);
-      const uint32_t key = key_f32(__float_as_uint(x[j]));
-      lds_inc_rare(dig, x[j] == x[j] && (key >> kShift1) == d1, (key >> kShift2) & 0xFFFu);
-      if (var_on) var(x[j], true);
+      if (j < ept_c) {  // uniform
+        if (hist_on) hacc(x[j], true);
+        const uint32_t key = key_f32(__float_as_uint(x[j]));
+        lds_inc_rare(dig, x[j] == x[j] && (key >> kShift1) == d1, (key >> kShift2) & 0xFFFu);
+        if (var_on) var(x[j], true);
+      }
     }
     if (var_on) block_store_var(var, sh.mom, &sh.part);
     __syncthreads();
@@ -448,8 +479,10 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
     const uint32_t p2 = prefix >> kShift2;
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
-      const uint32_t key = key_f32(__float_as_uint(x[j]));
-      lds_inc_rare(dig, x[j] == x[j] && (key >> kShift2) == p2, key & 0xFFu);
+      if (j < ept_c) {  // uniform
+        const uint32_t key = key_f32(__float_as_uint(x[j]));
+        lds_inc_rare(dig, x[j] == x[j] && (key >> kShift2) == p2, key & 0xFFu);
+      }
     }
     __syncthreads();
     found = block_select_small(dig, kBins3, k, sh, &d3, &cum, &bucket) && found;
@@ -479,8 +512,20 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
 
 // Values per lane needed for a cell of nvox voxels (0: more than the register path holds).
 int mm_ept(uint64_t nvox) {
-  for (int e : {8, 16, 24, 28, 32})
+  for (int e : {16, 32, 48, 56, 64})
     if (nvox <= (uint64_t)e * kMMBlock) return e;
+  return 0;
+}
+
+// Values per lane of the plane layout for a w x h x d cell (0: its face holds
+// more than 512 voxels or it needs more than 64 planes per lane).  Cells at
+// the cube's far edges are smaller, so they fit too.
+int mm_ept_plane(uint64_t w, uint64_t h, uint64_t d) {
+  if (w * h > (uint64_t)kMMBlock) return 0;
+  const uint64_t P = kMMBlock / (w * h);
+  const uint64_t need = (d + P - 1) / P;
+  for (int e : {16, 32, 48, 56, 64})
+    if (need <= (uint64_t)e) return e;
   return 0;
 }
 
@@ -511,7 +556,10 @@ int run_minimap(const tsa_cube* cube, int32_t cx, int32_t cy, int32_t cz, int32_
   hipStream_t s = (hipStream_t)stream;
   const uint64_t cell_vox = (uint64_t)(cx < cube->nx ? cx : cube->nx) * (uint64_t)(cy < cube->ny ? cy : cube->ny) *
                             (uint64_t)(cz < cube->nz ? cz : cube->nz);
-  const int ept = mm_ept(cell_vox);
+  const uint64_t cxe = (uint64_t)(cx < cube->nx ? cx : cube->nx), cye = (uint64_t)(cy < cube->ny ? cy : cube->ny),
+                 cze = (uint64_t)(cz < cube->nz ? cz : cube->nz);
+  const int ept_plane = mm_ept_plane(cxe, cye, cze);
+  const int ept = ept_plane ? ept_plane : mm_ept(cell_vox);
   if (ept && register_path_on()) {
     // histogram replicas: up to 16 per bin within 4096 counters
     uint32_t rshift = 0;
@@ -540,31 +588,33 @@ int run_minimap(const tsa_cube* cube, int32_t cx, int32_t cy, int32_t cz, int32_
     m.out = d_cells;
     m.hists = d_hists;
     const dim3 grid((uint32_t)(m.per_xcd * 8));
-#define TSA_MM_LAUNCH(DTV, EPTV) \
-  TSA_TRACED("minimap_cells", s, hipLaunchKernelGGL((k_mm_reg<DTV, EPTV>), grid, dim3(kMMBlock), lds, s, m))
+#define TSA_MM_LAUNCH(DTV, EPTV, PL) \
+  TSA_TRACED("minimap_cells", s, hipLaunchKernelGGL((k_mm_reg<DTV, EPTV, PL>), grid, dim3(kMMBlock), lds, s, m))
+#define TSA_MM_BY_EPT(DTV, PL)         \
+  do {                                 \
+    if (ept == 16)                     \
+      TSA_MM_LAUNCH(DTV, 16, PL);      \
+    else if (ept == 32)                \
+      TSA_MM_LAUNCH(DTV, 32, PL);      \
+    else if (ept == 48)                \
+      TSA_MM_LAUNCH(DTV, 48, PL);      \
+    else if (ept == 56)                \
+      TSA_MM_LAUNCH(DTV, 56, PL);      \
+    else                               \
+      TSA_MM_LAUNCH(DTV, 64, PL);      \
+  } while (0)
     if (cube->dtype == TSA_F32) {
-      if (ept == 8)
-        TSA_MM_LAUNCH(0, 8);
-      else if (ept == 16)
-        TSA_MM_LAUNCH(0, 16);
-      else if (ept == 24)
-        TSA_MM_LAUNCH(0, 24);
-      else if (ept == 28)
-        TSA_MM_LAUNCH(0, 28);
+      if (ept_plane)
+        TSA_MM_BY_EPT(0, true);
       else
-        TSA_MM_LAUNCH(0, 32);
+        TSA_MM_BY_EPT(0, false);
     } else {
-      if (ept == 8)
-        TSA_MM_LAUNCH(1, 8);
-      else if (ept == 16)
-        TSA_MM_LAUNCH(1, 16);
-      else if (ept == 24)
-        TSA_MM_LAUNCH(1, 24);
-      else if (ept == 28)
-        TSA_MM_LAUNCH(1, 28);
+      if (ept_plane)
+        TSA_MM_BY_EPT(1, true);
       else
-        TSA_MM_LAUNCH(1, 32);
+        TSA_MM_BY_EPT(1, false);
     }
+#undef TSA_MM_BY_EPT
 #undef TSA_MM_LAUNCH
     return hipGetLastError() == hipSuccess ? TSA_OK : TSA_EDEVICE;
   }
