@@ -3,7 +3,8 @@
 // threshold built from it: per cell, how many voxels lie above the cell's
 // mean + k standard deviations.
 //
-// Cells of at most 32768 voxels (a 30x30x30 cell is 27000) are answered by one
+// Cells whose rows hold at most 512 voxels and whose 512 / w rows per lane
+// cover the cell in 64 values (a 30x30x30 cell: 53) are answered by one
 // 512-lane workgroup each, the cell read from HBM once into registers (up to
 // 64 values per lane; at most ~100 registers a lane, so two workgroups share
 // a compute unit and one's loads and barriers overlap the other's counting):
@@ -285,15 +286,14 @@ struct MMShared {
 // so the cells one XCD (and its L2) sees are neighbours sharing cache lines at
 // their x edges.
 //
-// Two ways to spread a cell over the lanes.  PLANE (cells whose x*y face
-// holds at most 512 voxels, e.g. 16^3): lane t owns column t % w of row
-// (t / w) % h in z-slab t / (w h) of the face, P = 512 / (w h) slabs side by
-// side, and its values are that voxel in planes z, z + P, z + 2P, ...: one
-// constant address step, no per-value index arithmetic (lanes past P whole
-// faces hold NaN).  Otherwise lane t keeps voxels t + 512 j of the cell in
-// x-fastest order, stepping a (column, row, plane) cursor per value.
-// Value slots at or past the cell's own count ept_c skip every phase.
-template <int DT, int EPT, bool PLANE>
+// Lanes take whole rows of the cell: lane t owns column t % w, and with
+// R = 512 / w rows side by side it holds rows t / w, t / w + R, t / w + 2R,
+// ... of the cell's h * d rows (row r is y = r % h, z = r / h).  Each value is
+// one constant address step from the last, plus a plane carry when y wraps,
+// in 32-bit offsets from the cell's corner.  Slots past the cell (and lanes
+// past R whole rows) hold NaN; value slots at or past the cell's own count
+// ept_c skip every phase.
+template <int DT, int EPT>
 __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
   using T = typename Ty<DT>::T;
   extern __shared__ uint32_t lds[];  // digit counters [kBins1 + kTrash] | histogram [(nbins << rshift) + kTrash]
@@ -306,7 +306,7 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
   const uint32_t w = (uint32_t)(min(x0 + (int64_t)a.cx, a.nx) - x0);
   const uint32_t h = (uint32_t)(min(y0 + (int64_t)a.cy, a.ny) - y0);
   const uint32_t dd = (uint32_t)(min(z0 + (int64_t)a.cz, a.nz) - z0);
-  const uint32_t nvox = w * h * dd;  // <= EPT * kMMBlock (checked on the host)
+  const uint32_t nvox = w * h * dd;
   uint32_t* dig = lds;
   uint32_t* hist = lds + kBins1 + kTrash;
   const uint32_t hwords = ((uint32_t)a.nbins << a.rshift) + kTrash;
@@ -315,57 +315,35 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
 
   // 1. every load of the lane in flight at once
   float x[EPT];
-  int ept_c;  // value slots that can hold a voxel of this cell (the same in every lane)
-  const int64_t plane = a.nx * a.ny;
-  const T* base = (const T*)a.base + (z0 * plane + y0 * a.nx + x0);
+  const T* base = (const T*)a.base + (z0 * a.nx * a.ny + y0 * a.nx + x0);
   const Magic mw = w == (uint32_t)a.cx ? a.mx_full : a.mx_edge;
   const Magic mh = h == (uint32_t)a.cy ? a.my_full : a.my_edge;
-  if constexpr (PLANE) {
-    const uint32_t P = (uint32_t)kMMBlock / (w * h);  // >= 1: checked on the host for the full face
-    ept_c = (int)((dd + P - 1) / P);
-    const uint32_t row = mdiv((uint32_t)t, mw);
-    const uint32_t lx = (uint32_t)t - row * w, lz = mdiv(row, mh), ly = row - lz * h;
-    const T* p = base + ((int64_t)lz * plane + (int64_t)ly * a.nx + lx);
-    const int64_t step = (int64_t)P * plane;
-    const bool lane_in = lz < P;  // lanes past the P whole faces hold nothing
+  // a cell spans fewer than 2^31 elements of the cube (checked on the host)
+  const uint32_t nx32 = (uint32_t)a.nx, plane32 = (uint32_t)(a.nx * a.ny);
+  const uint32_t rows_side = (uint32_t)kMMBlock / w;  // w <= 512 (checked on the host)
+  const uint32_t nrows = h * dd;
+  const int ept_c = (int)__builtin_amdgcn_readfirstlane((nrows + rows_side - 1) / rows_side);
+  {
+    const uint32_t r0 = mdiv((uint32_t)t, mw);
+    const uint32_t lx = (uint32_t)t - r0 * w;
+    const uint32_t dz = mdiv(rows_side, mh), dy = rows_side - dz * h;  // rows_side = dz h + dy
+    const uint32_t lz = mdiv(r0, mh);
+    uint32_t ly = r0 - lz * h;
+    uint32_t off = lz * plane32 + ly * nx32 + lx;
+    const uint32_t step = dz * plane32 + dy * nx32;
+    const uint32_t wrap = plane32 - h * nx32;  // y passing h: one more plane, h rows back
+    const bool lane_in = r0 < rows_side;
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
-      if (lane_in && lz + (uint32_t)j * P < dd)  // planes past the cell never touch memory
-        x[j] = (float)p[j * step];
-      else
-        x[j] = __builtin_nanf("");
-    }
-  } else {
-    // voxel v = t + 512 j of the cell is (v % w, (v / w) % h, v / (w h)); the
-    // lane divides once, then steps by 512 voxels with constant increments
-    // and at most one carry per axis (no division in the loop)
-    ept_c = (int)((nvox + kMMBlock - 1) / kMMBlock);
-    const uint32_t dq = mdiv((uint32_t)kMMBlock, mw), dr = (uint32_t)kMMBlock - dq * w;
-    const uint32_t dqz = mdiv(dq, mh), dqy = dq - dqz * h;
-    const int64_t dstep = (int64_t)dqz * plane + (int64_t)dqy * a.nx + dr;
-    const uint32_t row0 = mdiv((uint32_t)t, mw);
-    uint32_t lx = (uint32_t)t - row0 * w, lz = mdiv(row0, mh), ly = row0 - lz * h;
-    int64_t off = (int64_t)lz * plane + (int64_t)ly * a.nx + lx;
-#pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-      const uint32_t v = (uint32_t)(j * kMMBlock + t);
-      if (v < nvox)  // slots past the cell never touch memory
+      if (lane_in && r0 + (uint32_t)j * rows_side < nrows)  // slots past the cell never touch memory
         x[j] = (float)base[off];
       else
         x[j] = __builtin_nanf("");
-      lx += dr;
-      ly += dqy;
-      lz += dqz;
-      off += dstep;
-      if (lx >= w) {
-        lx -= w;
-        ly += 1;
-        off += a.nx - (int64_t)w;
-      }
+      ly += dy;
+      off += step;
       if (ly >= h) {
         ly -= h;
-        lz += 1;
-        off += plane - (int64_t)h * a.nx;
+        off += wrap;
       }
     }
   }
@@ -440,7 +418,7 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
     }
   }
   __syncthreads();
-  if (sh.go) {
+  if (__builtin_amdgcn_readfirstlane(sh.go)) {
     // 2. first digit; histogram over [min, max] + second digit (+ M2 about the mean)
     uint32_t d1, d2, d3;
     uint32_t cum, bucket;  // a cell holds fewer than 2^32 voxels
@@ -450,14 +428,27 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
     __syncthreads();
     HistOwnAcc hacc{hist, sh.lo, sh.scale, a.nbins - 1, a.rshift, (uint32_t)t & ((1u << a.rshift) - 1u)};
     VarAcc var{sh.shift};
-    const bool hist_on = sh.hist_ok != 0, var_on = sh.var_on != 0;
+    // block-uniform switches, kept in scalar registers
+    const bool hist_on = __builtin_amdgcn_readfirstlane(sh.hist_ok) != 0;
+    const bool var_on = __builtin_amdgcn_readfirstlane(sh.var_on) != 0;
+    if (var_on) {  // rare: the second moment about the mean in the same sweep
 #pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-      if (j < ept_c) {  // uniform
-        if (hist_on) hacc(x[j], true);
-        const uint32_t key = key_f32(__float_as_uint(x[j]));
-        lds_inc_rare(dig, x[j] == x[j] && (key >> kShift1) == d1, (key >> kShift2) & 0xFFFu);
-        if (var_on) var(x[j], true);
+      for (int j = 0; j < EPT; ++j) {
+        if (j < ept_c) {
+          if (hist_on) hacc(x[j], true);
+          const uint32_t key = key_f32(__float_as_uint(x[j]));
+          lds_inc_rare(dig, x[j] == x[j] && (key >> kShift1) == d1, (key >> kShift2) & 0xFFFu);
+          var(x[j], true);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < EPT; ++j) {
+        if (j < ept_c) {
+          if (hist_on) hacc(x[j], true);
+          const uint32_t key = key_f32(__float_as_uint(x[j]));
+          lds_inc_rare(dig, x[j] == x[j] && (key >> kShift1) == d1, (key >> kShift2) & 0xFFFu);
+        }
       }
     }
     if (var_on) block_store_var(var, sh.mom, &sh.part);
@@ -510,20 +501,11 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
   }
 }
 
-// Values per lane needed for a cell of nvox voxels (0: more than the register path holds).
-int mm_ept(uint64_t nvox) {
-  for (int e : {16, 32, 48, 56, 64})
-    if (nvox <= (uint64_t)e * kMMBlock) return e;
-  return 0;
-}
-
-// Values per lane of the plane layout for a w x h x d cell (0: its face holds
-// more than 512 voxels or it needs more than 64 planes per lane).  Cells at
-// the cube's far edges are smaller, so they fit too.
-int mm_ept_plane(uint64_t w, uint64_t h, uint64_t d) {
-  if (w * h > (uint64_t)kMMBlock) return 0;
-  const uint64_t P = kMMBlock / (w * h);
-  const uint64_t need = (d + P - 1) / P;
+// Values per lane for a w x h x d cell (0: the register path does not hold
+// it): rows of w voxels, 512 / w rows side by side.
+int mm_ept(uint64_t w, uint64_t h, uint64_t d) {
+  if (w > (uint64_t)kMMBlock) return 0;
+  const uint64_t side = kMMBlock / w, need = (h * d + side - 1) / side;
   for (int e : {16, 32, 48, 56, 64})
     if (need <= (uint64_t)e) return e;
   return 0;
@@ -554,12 +536,11 @@ int run_minimap(const tsa_cube* cube, int32_t cx, int32_t cy, int32_t cz, int32_
   if (!need) return TSA_EINVAL;
   if (!d_ws || ws_bytes < need) return TSA_ENOMEM;
   hipStream_t s = (hipStream_t)stream;
-  const uint64_t cell_vox = (uint64_t)(cx < cube->nx ? cx : cube->nx) * (uint64_t)(cy < cube->ny ? cy : cube->ny) *
-                            (uint64_t)(cz < cube->nz ? cz : cube->nz);
   const uint64_t cxe = (uint64_t)(cx < cube->nx ? cx : cube->nx), cye = (uint64_t)(cy < cube->ny ? cy : cube->ny),
                  cze = (uint64_t)(cz < cube->nz ? cz : cube->nz);
-  const int ept_plane = mm_ept_plane(cxe, cye, cze);
-  const int ept = ept_plane ? ept_plane : mm_ept(cell_vox);
+  // 32-bit offsets inside a cell: its corner to its far corner
+  const bool span32 = (double)cze * (double)cube->nx * (double)cube->ny < 2147483648.0;
+  const int ept = span32 ? mm_ept(cxe, cye, cze) : 0;
   if (ept && register_path_on()) {
     // histogram replicas: up to 16 per bin within 4096 counters
     uint32_t rshift = 0;
@@ -588,32 +569,25 @@ int run_minimap(const tsa_cube* cube, int32_t cx, int32_t cy, int32_t cz, int32_
     m.out = d_cells;
     m.hists = d_hists;
     const dim3 grid((uint32_t)(m.per_xcd * 8));
-#define TSA_MM_LAUNCH(DTV, EPTV, PL) \
-  TSA_TRACED("minimap_cells", s, hipLaunchKernelGGL((k_mm_reg<DTV, EPTV, PL>), grid, dim3(kMMBlock), lds, s, m))
-#define TSA_MM_BY_EPT(DTV, PL)         \
-  do {                                 \
-    if (ept == 16)                     \
-      TSA_MM_LAUNCH(DTV, 16, PL);      \
-    else if (ept == 32)                \
-      TSA_MM_LAUNCH(DTV, 32, PL);      \
-    else if (ept == 48)                \
-      TSA_MM_LAUNCH(DTV, 48, PL);      \
-    else if (ept == 56)                \
-      TSA_MM_LAUNCH(DTV, 56, PL);      \
-    else                               \
-      TSA_MM_LAUNCH(DTV, 64, PL);      \
+#define TSA_MM_LAUNCH(DTV, EPTV) \
+  TSA_TRACED("minimap_cells", s, hipLaunchKernelGGL((k_mm_reg<DTV, EPTV>), grid, dim3(kMMBlock), lds, s, m))
+#define TSA_MM_BY_EPT(DTV)         \
+  do {                             \
+    if (ept == 16)                 \
+      TSA_MM_LAUNCH(DTV, 16);      \
+    else if (ept == 32)            \
+      TSA_MM_LAUNCH(DTV, 32);      \
+    else if (ept == 48)            \
+      TSA_MM_LAUNCH(DTV, 48);      \
+    else if (ept == 56)            \
+      TSA_MM_LAUNCH(DTV, 56);      \
+    else                           \
+      TSA_MM_LAUNCH(DTV, 64);      \
   } while (0)
-    if (cube->dtype == TSA_F32) {
-      if (ept_plane)
-        TSA_MM_BY_EPT(0, true);
-      else
-        TSA_MM_BY_EPT(0, false);
-    } else {
-      if (ept_plane)
-        TSA_MM_BY_EPT(1, true);
-      else
-        TSA_MM_BY_EPT(1, false);
-    }
+    if (cube->dtype == TSA_F32)
+      TSA_MM_BY_EPT(0);
+    else
+      TSA_MM_BY_EPT(1);
 #undef TSA_MM_BY_EPT
 #undef TSA_MM_LAUNCH
     return hipGetLastError() == hipSuccess ? TSA_OK : TSA_EDEVICE;
