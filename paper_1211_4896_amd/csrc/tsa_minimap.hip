@@ -348,13 +348,25 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
     }
   }
   __syncthreads();  // counters cleared
-  // moments, min/max keys and the first key digit
+  // moments, min/max keys and the first key digit.  The per-value steps are
+  // written out here rather than through the shared accumulators: every step
+  // sits under the value's own NaN test, so no select is needed, and the
+  // digit counters need no wave vote (a wave with no matching lane skips the
+  // masked LDS increment by its exec mask).
   MomAcc<0, false> mom;  // the count is the first-digit histogram's total
 #pragma unroll
   for (int j = 0; j < EPT; ++j) {
     if (j < ept_c) {  // uniform
-      mom(x[j], true);
-      if (x[j] == x[j]) lds_inc(dig, key_f32(__float_as_uint(x[j])) >> kShift1);
+      const float v = x[j];
+      if (v == v) {
+        const double d = (double)v;
+        mom.s += d;
+        mom.q = __builtin_fma(d, d, mom.q);
+        const uint32_t k = key_f32(__float_as_uint(v));
+        mom.kmin = min(mom.kmin, k);
+        mom.kmax = max(mom.kmax, k);
+        lds_inc(dig, k >> kShift1);
+      }
     }
   }
   __syncthreads();
@@ -426,31 +438,36 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
     uint32_t k = (uint32_t)sh.k - cum;
     for (uint32_t i = t; i < kBins2; i += kMMBlock) dig[i] = 0u;
     __syncthreads();
-    HistOwnAcc hacc{hist, sh.lo, sh.scale, a.nbins - 1, a.rshift, (uint32_t)t & ((1u << a.rshift) - 1u)};
+    // histogram over [min, max] (the formula of HistOwnAcc: b = min((int)((v -
+    // lo) * scale), nbins - 1), replica lane % R of bin b) + second digit
+    const float lo = sh.lo, scale = sh.scale;
+    const int32_t nbm1 = a.nbins - 1;
+    const uint32_t rshift = a.rshift;
+    uint32_t* hrep = hist + ((uint32_t)t & ((1u << rshift) - 1u));
     VarAcc var{sh.shift};
     // block-uniform switches, kept in scalar registers
     const bool hist_on = __builtin_amdgcn_readfirstlane(sh.hist_ok) != 0;
     const bool var_on = __builtin_amdgcn_readfirstlane(sh.var_on) != 0;
-    if (var_on) {  // rare: the second moment about the mean in the same sweep
-#pragma unroll
-      for (int j = 0; j < EPT; ++j) {
-        if (j < ept_c) {
-          if (hist_on) hacc(x[j], true);
-          const uint32_t key = key_f32(__float_as_uint(x[j]));
-          lds_inc_rare(dig, x[j] == x[j] && (key >> kShift1) == d1, (key >> kShift2) & 0xFFFu);
-          var(x[j], true);
-        }
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < EPT; ++j) {
-        if (j < ept_c) {
-          if (hist_on) hacc(x[j], true);
-          const uint32_t key = key_f32(__float_as_uint(x[j]));
-          lds_inc_rare(dig, x[j] == x[j] && (key >> kShift1) == d1, (key >> kShift2) & 0xFFFu);
-        }
-      }
-    }
+#define TSA_MM_PASS2(VAR_STEP)                                                \
+  _Pragma("unroll") for (int j = 0; j < EPT; ++j) {                           \
+    if (j < ept_c) {                                                          \
+      const float v = x[j];                                                   \
+      if (v == v) {                                                           \
+        if (hist_on) {                                                        \
+          const float tb = (v - lo) * scale; /* lo == hi: scale 0, tb 0 */    \
+          lds_inc(hrep, (uint32_t)min((int32_t)tb, nbm1) << rshift);          \
+        }                                                                     \
+        const uint32_t k = key_f32(__float_as_uint(v));                       \
+        if ((k >> kShift1) == d1) lds_inc(dig, (k >> kShift2) & 0xFFFu);      \
+        VAR_STEP;                                                             \
+      }                                                                       \
+    }                                                                         \
+  }
+    if (var_on)  // rare: the second moment about the mean in the same sweep
+      TSA_MM_PASS2(var(v, true))
+    else
+      TSA_MM_PASS2((void)0)
+#undef TSA_MM_PASS2
     if (var_on) block_store_var(var, sh.mom, &sh.part);
     __syncthreads();
     if (t == 0 && var_on) {
@@ -471,8 +488,11 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
       if (j < ept_c) {  // uniform
-        const uint32_t key = key_f32(__float_as_uint(x[j]));
-        lds_inc_rare(dig, x[j] == x[j] && (key >> kShift2) == p2, key & 0xFFu);
+        const float v = x[j];
+        if (v == v) {
+          const uint32_t k = key_f32(__float_as_uint(v));
+          if ((k >> kShift2) == p2) lds_inc(dig, k & 0xFFu);
+        }
       }
     }
     __syncthreads();
