@@ -291,8 +291,7 @@ struct MMShared {
 // ... of the cell's h * d rows (row r is y = r % h, z = r / h).  Each value is
 // one constant address step from the last, plus a plane carry when y wraps,
 // in 32-bit offsets from the cell's corner.  Slots past the cell (and lanes
-// past R whole rows) hold NaN; value slots at or past the cell's own count
-// ept_c skip every phase.
+// past R whole rows) hold NaN and drop out at each step's NaN test.
 template <int DT, int EPT>
 __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
   using T = typename Ty<DT>::T;
@@ -322,7 +321,6 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
   const uint32_t nx32 = (uint32_t)a.nx, plane32 = (uint32_t)(a.nx * a.ny);
   const uint32_t rows_side = (uint32_t)kMMBlock / w;  // w <= 512 (checked on the host)
   const uint32_t nrows = h * dd;
-  const int ept_c = (int)__builtin_amdgcn_readfirstlane((nrows + rows_side - 1) / rows_side);
   {
     const uint32_t r0 = mdiv((uint32_t)t, mw);
     const uint32_t lx = (uint32_t)t - r0 * w;
@@ -356,7 +354,7 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
   MomAcc<0, false> mom;  // the count is the first-digit histogram's total
 #pragma unroll
   for (int j = 0; j < EPT; ++j) {
-    if (j < ept_c) {  // uniform
+    {
       const float v = x[j];
       if (v == v) {
         const double d = (double)v;
@@ -370,6 +368,12 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
     }
   }
   __syncthreads();
+  // The values' NaN tests are repeated in the later sweeps rather than kept:
+  // an empty register barrier stops the compiler from holding 2 scalar
+  // registers of lane mask per value across the phases (it spills them to
+  // vector lanes, which costs more than the compare).
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) asm volatile("" : "+v"(x[j]));
   {
     uint32_t c = 0;
     for (uint32_t i = t; i < kBins1; i += kMMBlock) c += dig[i];
@@ -450,7 +454,7 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
     const bool var_on = __builtin_amdgcn_readfirstlane(sh.var_on) != 0;
 #define TSA_MM_PASS2(VAR_STEP)                                                \
   _Pragma("unroll") for (int j = 0; j < EPT; ++j) {                           \
-    if (j < ept_c) {                                                          \
+    {                                                                         \
       const float v = x[j];                                                   \
       if (v == v) {                                                           \
         if (hist_on) {                                                        \
@@ -486,8 +490,10 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
     __syncthreads();
     const uint32_t p2 = prefix >> kShift2;
 #pragma unroll
+    for (int j = 0; j < EPT; ++j) asm volatile("" : "+v"(x[j]));
+#pragma unroll
     for (int j = 0; j < EPT; ++j) {
-      if (j < ept_c) {  // uniform
+      {
         const float v = x[j];
         if (v == v) {
           const uint32_t k = key_f32(__float_as_uint(v));
