@@ -16,7 +16,8 @@
  *   - runs full-cube histogram and median requests on a stream of their own,
  *     overlapping the region batches on the device; every full-cube request
  *     admitted for one cube is answered by one shared scan of that cube (one
- *     histogram pass, the two radix passes, or the fused two-pass trio);
+ *     histogram pass, the radix passes, or the fused two-pass trio), its
+ *     passes cut into z-slab launches of a voxel budget when one is set;
  *   - retires finished work by polling events and timestamps every stage.
  * Each request's result depends only on its own cube and box, never on what
  * else is in flight.
@@ -41,7 +42,10 @@ typedef struct {
   int32_t max_admitted;   /* requests admitted (holding scratch) at once, >= 1 */
   int32_t region_nbins;   /* bins of a region request's histogram over its own [min,max], 1..4096 */
   int32_t full_nbins;     /* bins of a full-cube histogram over the cube's [min,max], 1..65536 */
-  int32_t reserved;       /* must be 0 */
+  int32_t full_chunk_kvoxels; /* voxels (in units of 1024) per kernel launch of a full-cube scan's passes:
+                                 each pass over a cube goes out as one launch per z-slab of at most that
+                                 many voxels, so region batches can start between them; 0 = one launch
+                                 per pass (the fused two-pass trio when both kinds share a scan) */
   size_t scratch_bytes;   /* admission budget of device scratch, bytes (0 = no limit beyond the slots) */
 } tsa_server_config;
 

@@ -78,6 +78,11 @@ int run_mad(const tsa_cube* cube, const tsa_region* region, double* d_out, void*
             tsa_stream_t stream);
 int run_stats(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa_result* d_out, uint64_t* d_counts,
               uint64_t* d_outliers, void* d_ws, size_t ws_bytes, tsa_stream_t stream);
+int run_histogram_chunked(const tsa_cube* cube, float lo, float hi, int32_t nbins, uint64_t* d_counts,
+                          uint64_t* d_outliers, void* d_ws, size_t ws_bytes, tsa_stream_t stream,
+                          int64_t chunk_voxels);
+int run_median_chunked(const tsa_cube* cube, tsa_result* d_out, void* d_ws, size_t ws_bytes, tsa_stream_t stream,
+                       int64_t chunk_voxels);
 int run_stats_static(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa_result* d_out,
                      uint64_t* d_counts, uint64_t* d_outliers, tsa_stream_t stream);
 size_t stats_static_scratch_bytes();

@@ -3,6 +3,7 @@
 #include <math.h>
 
 #include <mutex>
+#include <vector>
 
 #include "tsa_internal.hpp"
 
@@ -83,11 +84,13 @@ __global__ __launch_bounds__(1024) void k_level2(Geom g, SelState* __restrict__ 
 }
 
 // Level 3 reads the candidate list when level 2 made one, else the cube.
+// first = 0: one more slab of a scan cut into slabs (the candidates, when
+// there are any, were counted with the first).
 template <int DT, bool VEC, bool NT>
 __global__ __launch_bounds__(1024) void k_level3(Geom g, SelState* __restrict__ st, uint64_t* __restrict__ hist3,
-                                                 const uint32_t* __restrict__ cand) {
+                                                 const uint32_t* __restrict__ cand, int first) {
   __shared__ uint32_t lds[kBins3];
-  if (st->done) return;
+  if (st->done || (st->compact && !first)) return;
   lds_zero(lds, kBins3);
   __syncthreads();
   const uint32_t p2 = st->prefix >> kShift2;
@@ -1072,7 +1075,7 @@ static int launch_median_tail(const tsa_cube* cube, const Prep& P, tsa_result* d
   TSA_TRACED("level3", P.s,
     TSA_DISPATCH(cube->dtype, P.vec, tuning().nt,
                  hipLaunchKernelGGL((k_level3<DT, VEC, NT>), dim3(P.grid), dim3(P.block), 0, P.s, P.g, stp, h3,
-                                    (const uint32_t*)cand)));
+                                    (const uint32_t*)cand, 1)));
   TSA_TRACED("select", P.s,
              hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, P.s, 3, (const uint64_t*)h3, stp, cube->dtype,
                                 (uint64_t)P.volume, d_out, (int)write_counts, qout));
@@ -1102,6 +1105,119 @@ int run_median(const tsa_cube* cube, const tsa_region* region, tsa_result* d_out
     TSA_DISPATCH(cube->dtype, P.vec, tuning().nt,
                  hipLaunchKernelGGL((k_level2<DT, VEC, NT>), dim3(P.grid), dim3(P.block), 0, P.s, P.g, stp, h2, cand)));
   return launch_median_tail(cube, P, d_out, true);
+}
+
+// ---------------------------------------------------------------------------
+// Whole-cube scans cut into z-slabs of at most chunk_voxels voxels: every
+// pass over the data goes out as one launch per slab, so a device shared
+// with other streams (the serving loop's region batches) can start their
+// work between two launches of a long scan.  The same kernels accumulate
+// their counters across the slabs, so the results are the same as one
+// launch per pass gives.
+// ---------------------------------------------------------------------------
+struct Slab {
+  Geom g;
+  bool vec;
+  int grid;
+};
+
+static int slabs_of(const tsa_cube* cube, int64_t chunk_voxels, const Prep& P, std::vector<Slab>* out) {
+  const int64_t plane = cube->nx * cube->ny;
+  int64_t planes = chunk_voxels / plane;
+  if (planes < 1) planes = 1;
+  int maxb = P.dev.cus * P.bpc;
+  if (maxb > kMaxBlocks) maxb = kMaxBlocks;
+  for (int64_t z0 = 0; z0 < cube->nz; z0 += planes) {
+    const tsa_region b{0, 0, z0, cube->nx, cube->ny, z0 + planes < cube->nz ? z0 + planes : cube->nz};
+    Slab sl;
+    int64_t vol = 0;
+    const int st = make_geom(cube, b, kTileUnits, &sl.g, &sl.vec, &vol);
+    if (st) return st;
+    sl.grid = pass_grid(sl.g, sl.vec, P.block, maxb);
+    out->push_back(sl);
+  }
+  return TSA_OK;
+}
+
+int run_histogram_chunked(const tsa_cube* cube, float lo, float hi, int32_t nbins, uint64_t* d_counts,
+                          uint64_t* d_outliers, void* d_ws, size_t ws_bytes, tsa_stream_t stream,
+                          int64_t chunk_voxels) {
+  if (!d_counts || chunk_voxels < 1) return TSA_EINVAL;
+  if (nbins < 1 || nbins > 65536) return TSA_EINVAL;
+  if (!isfinite(lo) || !isfinite(hi) || lo > hi) return TSA_EINVAL;
+  float scale = 0.0f;
+  if (lo < hi) {
+    volatile float width = hi - lo;
+    if (!isfinite(width)) return TSA_EINVAL;
+    volatile float sc = (float)nbins / width;
+    if (!isfinite(sc) || sc == 0.0f) return TSA_EINVAL;
+    scale = sc;
+  }
+  Prep P;
+  int st = prepare(cube, nullptr, d_ws, ws_bytes, stream, &P, kBpcHist);
+  if (st) return st;
+  std::vector<Slab> slabs;
+  if ((st = slabs_of(cube, chunk_voxels, P, &slabs))) return st;
+  uint64_t* outl = d_outliers ? d_outliers : (uint64_t*)(P.ws + P.L.outl);
+  fill32(d_counts, (size_t)nbins * 2, 0u, P.s);
+  fill32(outl, 4, 0u, P.s);
+  const size_t budget = P.dev.lds_per_block < 65536 ? P.dev.lds_per_block : 65536;
+  const uint32_t rs = rep_shift_for(nbins, budget);
+  const size_t lds = (((size_t)nbins << rs) + kTrash) * 4;
+  for (const Slab& sl : slabs) {
+    if (lds <= budget) {
+      TSA_TRACED("hist", P.s,
+        TSA_DISPATCH(cube->dtype, sl.vec, tuning().nt,
+                     hipLaunchKernelGGL((k_hist<DT, VEC, NT>), dim3(sl.grid), dim3(P.block), lds, P.s, sl.g, lo, hi,
+                                        scale, nbins, rs, d_counts, outl)));
+    } else if ((st = run_histogram_wide(cube, sl.g, sl.vec, sl.grid, P.block, lo, hi, scale, nbins, d_counts, outl,
+                                        P.s))) {
+      return st;
+    }
+  }
+  return launch_ok();
+}
+
+int run_median_chunked(const tsa_cube* cube, tsa_result* d_out, void* d_ws, size_t ws_bytes, tsa_stream_t stream,
+                       int64_t chunk_voxels) {
+  if (!d_out || chunk_voxels < 1) return TSA_EINVAL;
+  Prep P;
+  int st = prepare(cube, nullptr, d_ws, ws_bytes, stream, &P, kBpcSelect);
+  if (st) return st;
+  std::vector<Slab> slabs;
+  if ((st = slabs_of(cube, chunk_voxels, P, &slabs))) return st;
+  reset_select(P);
+  SelState* stp = (SelState*)(P.ws + P.L.state);
+  uint64_t* h1 = (uint64_t*)(P.ws + P.L.hist1);
+  uint64_t* h2 = (uint64_t*)(P.ws + P.L.hist2);
+  uint64_t* h3 = (uint64_t*)(P.ws + P.L.hist3);
+  uint32_t* cand = (uint32_t*)(P.ws + P.L.cand);
+  const uint32_t rs = rep_shift_for(kBins1, 32768);
+  for (const Slab& sl : slabs)
+    TSA_TRACED("level1", P.s,
+      TSA_DISPATCH(cube->dtype, sl.vec, tuning().nt,
+                   hipLaunchKernelGGL((k_level1<DT, VEC, NT>), dim3(sl.grid), dim3(P.block),
+                                      (((size_t)kBins1 << rs) + kTrash) * 4, P.s, sl.g, rs, h1)));
+  TSA_TRACED("select", P.s,
+             hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, P.s, 1, (const uint64_t*)h1, stp, cube->dtype,
+                                (uint64_t)P.volume, d_out, 1, (double*)nullptr));
+  for (const Slab& sl : slabs)
+    TSA_TRACED("level2", P.s,
+      TSA_DISPATCH(cube->dtype, sl.vec, tuning().nt,
+                   hipLaunchKernelGGL((k_level2<DT, VEC, NT>), dim3(sl.grid), dim3(P.block), 0, P.s, sl.g, stp, h2,
+                                      cand)));
+  TSA_TRACED("select", P.s,
+             hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, P.s, 2, (const uint64_t*)h2, stp, cube->dtype,
+                                (uint64_t)P.volume, d_out, 1, (double*)nullptr));
+  for (size_t i = 0; i < slabs.size(); ++i)
+    TSA_TRACED("level3", P.s,
+      TSA_DISPATCH(cube->dtype, slabs[i].vec, tuning().nt,
+                   hipLaunchKernelGGL((k_level3<DT, VEC, NT>), dim3(slabs[i].grid), dim3(P.block), 0, P.s,
+                                      slabs[i].g, stp, h3, (const uint32_t*)cand, i == 0 ? 1 : 0)));
+  TSA_TRACED("select", P.s,
+             hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, P.s, 3, (const uint64_t*)h3, stp, cube->dtype,
+                                (uint64_t)P.volume, d_out, 1, (double*)nullptr));
+  return launch_ok();
 }
 
 static int enqueue_stats(const tsa_cube* cube, const tsa_region* region, int32_t nbins, tsa_result* d_out,

@@ -15,7 +15,8 @@ REQ_REGION, REQ_FULL_HIST, REQ_FULL_MEDIAN = 0, 1, 2
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("max_batch", ctypes.c_int32), ("region_lanes", ctypes.c_int32), ("max_admitted", ctypes.c_int32),
-                ("region_nbins", ctypes.c_int32), ("full_nbins", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("region_nbins", ctypes.c_int32), ("full_nbins", ctypes.c_int32),
+                ("full_chunk_kvoxels", ctypes.c_int32),
                 ("scratch_bytes", ctypes.c_size_t)]
 
 
@@ -73,9 +74,10 @@ class Server:
     """A serving engine over resident cubes (torch tensors kept alive here)."""
 
     def __init__(self, max_batch=1024, region_lanes=2, max_admitted=4096, region_nbins=256, full_nbins=4096,
-                 scratch_bytes=0):
+                 scratch_bytes=0, full_chunk_kvoxels=0):
         self.lib = _bind()
-        self.cfg = ServerConfig(max_batch, region_lanes, max_admitted, region_nbins, full_nbins, 0, scratch_bytes)
+        self.cfg = ServerConfig(max_batch, region_lanes, max_admitted, region_nbins, full_nbins, full_chunk_kvoxels,
+                                scratch_bytes)
         h = ctypes.c_void_p()
         st = self.lib.tsa_server_create(ctypes.byref(self.cfg), ctypes.byref(h))
         if st != TSA_OK:

@@ -98,7 +98,7 @@ def test_server_config_rejected_before_device():
     for bad in [serve.ServerConfig(0, 1, 1, 8, 8, 0, 0), serve.ServerConfig(8, 0, 1, 8, 8, 0, 0),
                 serve.ServerConfig(8, 5, 1, 8, 8, 0, 0), serve.ServerConfig(8, 1, 0, 8, 8, 0, 0),
                 serve.ServerConfig(8, 1, 1, 5000, 8, 0, 0), serve.ServerConfig(8, 1, 1, 8, 70000, 0, 0),
-                serve.ServerConfig(8, 1, 1, 8, 8, 1, 0)]:
+                serve.ServerConfig(8, 1, 1, 8, 8, -1, 0)]:
         assert lib.tsa_server_create(ctypes.byref(bad), ctypes.byref(h)) == tsa.TSA_EINVAL
     assert lib.tsa_server_now() > 0
 

@@ -181,3 +181,47 @@ def test_scratch_budget_limits_admission():
             assert len(a) == 1 and out[i].status == 0
             assert _same(a[0], out[i]), (i, reqs[i])
             assert np.array_equal(alone_h[i], mh[i]), i
+
+
+def test_full_scans_in_slab_launches():
+    """Full-cube requests answered with each pass cut into z-slab launches of
+    a voxel budget (17 KiB voxels here: many slabs, the last one short; the
+    median's candidate list and its third pass over the slabs, a histogram of
+    more bins than one LDS copy holds) give the same bits as one launch per
+    pass, and the oracle's answers."""
+    rng = np.random.default_rng(12)
+    hosts = [synth.generate(synth.scaled(synth.SPECS["c5a"], 64, 48, 40))[0],
+             rng.integers(0, 3, size=(37, 40, 64)).astype(np.float32),  # ties: the last digit over the slabs
+             synth.generate(synth.scaled(synth.SPECS["c5c"], 64, 32, 33))[0]]
+    devs = [torch.from_numpy(h).to("cuda:0") for h in hosts]
+    kinds = [serve.REQ_FULL_HIST, serve.REQ_FULL_MEDIAN]
+    for nbins in (512, 20000):
+        outs = []
+        for chunk in (0, 17):
+            with serve.Server(max_batch=8, region_lanes=1, max_admitted=64, region_nbins=16, full_nbins=nbins,
+                              full_chunk_kvoxels=chunk) as srv:
+                ids = [srv.add_cube(d) for d in devs]
+                reqs = [(c, k, None) for c in range(len(hosts)) for k in kinds]
+                mk, mh = _make(srv, ids, reqs, 16, nbins)
+                _say("case serve slabs", nbins, chunk)
+                for r in mk:
+                    srv.submit(r)
+                srv.drain(60.0)
+                got = sorted(srv.poll(64), key=lambda r: r.tag)
+                assert len(got) == len(reqs) and all(g.status == 0 for g in got)
+                outs.append((got, mh))
+        (a, ah), (b, bh) = outs
+        for i, (c, kind, _) in enumerate(reqs):
+            assert _same(a[i], b[i]), (nbins, i)
+            assert np.array_equal(ah[i], bh[i]), (nbins, i)
+            host = hosts[c]
+            dt = "i16" if host.dtype == np.int16 else "f32"
+            r = serve.response_dict(b[i])["result"]
+            if kind == serve.REQ_FULL_MEDIAN:
+                want, n = oracle.median(host)
+                check_median(r["median"], want, dt, f"slabs median {c}")
+                assert r["count"] == n
+            else:
+                mo = oracle.moments(host)
+                wc, _ = oracle.histogram(host, float(np.float32(mo["min"])), float(np.float32(mo["max"])), nbins)
+                check_hist(bh[i], None, wc, None, f"slabs hist {c} {nbins}")
