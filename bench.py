@@ -213,6 +213,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-warmup", type=float, default=10.0)
     ap.add_argument("--serve-qps", type=float, default=2000.0)
+    ap.add_argument("--serve-chunk-kvoxels", type=int, default=0,
+                    help="voxels (x1024) per launch of a full-cube scan's passes in the serving run (0: one launch)")
     ap.add_argument("--no-minimap", action="store_true", help="skip the mini-map + k-sigma measurement")
     ap.add_argument("--no-spectrum", action="store_true", help="skip the spectrum-tool measurement")
     ap.add_argument("--no-c1", action="store_true", help="skip the 256^3 cache-resident case")
@@ -297,7 +299,8 @@ def main():
         line["region_batch"] = _region_batch_bench(tsa, torch, np, synth, args.region_reps)
         torch.cuda.empty_cache()
     if not args.no_serve:
-        line["serving"] = _serving_bench(torch, np, synth, args.serve_seconds, args.serve_qps, args.serve_warmup)
+        line["serving"] = _serving_bench(torch, np, synth, args.serve_seconds, args.serve_qps, args.serve_warmup,
+                                         args.serve_chunk_kvoxels)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = _cpu_baseline(spec, nbins)
@@ -528,7 +531,7 @@ def _spectrum_bench(tsa, torch, np, synth, api, lib, dev, sh, reps: int) -> dict
             "gathered_gb_s": round((32.0 * inside + 8.0 * ns) / (kms * 1e-3) / 1e9, 1)}
 
 
-def _serving_bench(torch, np, synth, seconds: float, qps: float, warm: float = 10.0) -> dict:
+def _serving_bench(torch, np, synth, seconds: float, qps: float, warm: float = 10.0, chunk_kvoxels: int = 0) -> dict:
     """c5: open-loop Poisson arrivals over three resident cubes (float32 1024^3,
     float32 2048x2048x1024, int16 2048^3): 90% region requests (c4 boxes), 10%
     full-cube requests (half 4096-bin histograms over the cube's [min,max],
@@ -545,7 +548,8 @@ def _serving_bench(torch, np, synth, seconds: float, qps: float, warm: float = 1
     n = int((warm + seconds) * qps)
     rng = np.random.default_rng(77)
     t_arr = serve.poisson_arrivals(qps, n, seed=78)
-    srv = serve.Server(max_batch=1024, region_lanes=2, max_admitted=8192, region_nbins=256, full_nbins=4096)
+    srv = serve.Server(max_batch=1024, region_lanes=2, max_admitted=8192, region_nbins=256, full_nbins=4096,
+                       full_chunk_kvoxels=chunk_kvoxels)
     try:
         ids = [srv.add_cube(d) for d in devs]
         reqs = []
@@ -589,6 +593,7 @@ def _serving_bench(torch, np, synth, seconds: float, qps: float, warm: float = 1
     return {"workload": "c5: float32 1024^3 + float32 2048x2048x1024 + int16 2048^3 resident; Poisson arrivals; 90% "
                         "region (c4 boxes, 256 bins), 5% full-cube 4096-bin histogram, 5% full-cube median",
             "offered_qps": qps, "measured_s": seconds, "warmup_s": warm, "requests": len(keep),
+            "full_scan_launch_voxels": chunk_kvoxels * 1024,
             "achieved_qps": round(len(keep) / (t_last - t_first), 1),
             "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "p999_ms": pct(lat, 99.9),
             "p50_region_ms": pct(lat[kinds == 0], 50), "p99_region_ms": pct(lat[kinds == 0], 99),
