@@ -55,6 +55,83 @@ __global__ __launch_bounds__(1024) void k_hist(Geom g, float lo, float hi, float
 }
 
 // ---------------------------------------------------------------------------
+// histograms of more bins than one LDS copy holds (the standalone call)
+// ---------------------------------------------------------------------------
+// Where the window of kWinBins 32-bit LDS counters goes: one block bins a
+// sample of 64 voxels per lane spread evenly over the region (the stated
+// formula), counts them per group of nbins/256 bins, and writes the first bin
+// of the run of groups that holds the most samples.  Only the placement
+// depends on the sample; k_hist_win counts every voxel exactly wherever the
+// window is.
+constexpr int kPlaceThreads = 1024, kPlacePerLane = 64;
+
+template <int DT>
+__global__ __launch_bounds__(kPlaceThreads) void k_hist_place(const void* base, int64_t nx, int64_t ny, tsa_region b,
+                                                              float lo, float hi, float scale, int32_t nbins,
+                                                              int32_t* __restrict__ w0_out) {
+  using T = typename Ty<DT>::T;
+  __shared__ uint32_t coarse[256];
+  uint32_t gshift = 0;  // bins per group: 2^gshift, at most 256 groups
+  while (((uint32_t)(nbins - 1) >> gshift) >= 256u) ++gshift;
+  for (int i = threadIdx.x; i < 256; i += blockDim.x) coarse[i] = 0u;
+  __syncthreads();
+  const int64_t lx = b.x1 - b.x0, ly = b.y1 - b.y0, lz = b.z1 - b.z0;
+  const uint64_t vol = (uint64_t)lx * (uint64_t)ly * (uint64_t)lz;
+  const uint64_t ns = (uint64_t)kPlaceThreads * kPlacePerLane;
+  for (int k = 0; k < kPlacePerLane; ++k) {
+    const uint64_t s = (uint64_t)k * kPlaceThreads + threadIdx.x;
+    const uint64_t i = (uint64_t)(((unsigned __int128)s * vol) / ns);  // < vol
+    const int64_t x = (int64_t)(i % (uint64_t)lx), r = (int64_t)(i / (uint64_t)lx);
+    const int64_t y = r % ly, z = r / ly;
+    const float v = (float)((const T*)base)[(b.z0 + z) * nx * ny + (b.y0 + y) * nx + (b.x0 + x)];
+    if (v >= lo && v <= hi) {
+      const int32_t bin = min(max((int32_t)((v - lo) * scale), 0), nbins - 1);
+      atomicAdd(&coarse[(uint32_t)bin >> gshift], 1u);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int32_t ngroups = (int32_t)(((uint32_t)(nbins - 1) >> gshift) + 1);
+    const int32_t wg = min((int32_t)(kWinBins >> gshift), ngroups);  // groups the window spans
+    uint32_t run = 0;
+    for (int32_t g = 0; g < wg; ++g) run += coarse[g];
+    uint32_t best = run;
+    int32_t best_g = 0;
+    for (int32_t g = 1; g + wg <= ngroups; ++g) {
+      run += coarse[g + wg - 1];
+      run -= coarse[g - 1];
+      if (run > best) {
+        best = run;
+        best_g = g;
+      }
+    }
+    int32_t w0 = best_g << gshift;
+    if (w0 > nbins - (int32_t)kWinBins) w0 = max(nbins - (int32_t)kWinBins, 0);
+    *w0_out = w0;
+  }
+}
+
+template <int DT, bool VEC, bool NT>
+__global__ __launch_bounds__(1024) void k_hist_win(Geom g, float lo, float hi, float scale, int32_t nbins,
+                                                   const int32_t* __restrict__ w0p, uint64_t* __restrict__ counts,
+                                                   uint64_t* __restrict__ outl) {
+  extern __shared__ uint32_t lds[];  // kWinBins window counters
+  __shared__ uint32_t osm[32];
+  const int32_t w0 = *w0p;
+  lds_zero(lds, kWinBins);
+  __syncthreads();
+  HistWinOutAcc h{lds, lo, hi, scale, nbins - 1, w0, counts};
+  walk<DT, VEC, kUnroll, NT>(g, h);
+  __syncthreads();
+  const uint32_t nw = (uint32_t)min((int32_t)kWinBins, nbins - w0);
+  for (uint32_t i = threadIdx.x; i < nw; i += blockDim.x) {
+    const uint32_t c = lds[i];
+    if (c) atomicAdd((unsigned long long*)(counts + w0 + i), (unsigned long long)c);
+  }
+  block_add_outliers(h.below, h.above, outl, osm);
+}
+
+// ---------------------------------------------------------------------------
 // radix selection: level passes over the cube
 // ---------------------------------------------------------------------------
 template <int DT, bool VEC, bool NT>
@@ -1015,6 +1092,18 @@ static int launch_pass_bwin(const Prep& P, int block, int grid, size_t lds, int3
   return TSA_OK;
 }
 
+template <int DT, bool VEC, bool NT>
+static int launch_hist_win(const Prep& P, int grid, size_t lds, float lo, float hi, float scale, int32_t nbins,
+                           const int32_t* w0p, uint64_t* d_counts, uint64_t* outl) {
+  if (hipFuncSetAttribute((const void*)k_hist_win<DT, VEC, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)lds) != hipSuccess)
+    return TSA_EDEVICE;
+  TSA_TRACED("hist_win", P.s,
+             hipLaunchKernelGGL((k_hist_win<DT, VEC, NT>), dim3(grid), dim3(1024), lds, P.s, P.g, lo, hi, scale,
+                                nbins, w0p, d_counts, outl));
+  return TSA_OK;
+}
+
 int run_moments(const tsa_cube* cube, const tsa_region* region, tsa_result* d_out, void* d_ws, size_t ws_bytes,
                 tsa_stream_t stream) {
   if (!d_out) return TSA_EINVAL;
@@ -1058,6 +1147,27 @@ int run_histogram(const tsa_cube* cube, const tsa_region* region, float lo, floa
     TSA_DISPATCH(cube->dtype, P.vec, tuning().nt,
                    hipLaunchKernelGGL((k_hist<DT, VEC, NT>), dim3(P.grid), dim3(P.block), lds, P.s, P.g, lo, hi, scale,
                                       nbins, rs, d_counts, outl)));
+    return launch_ok();
+  }
+  // a window of 32-bit counters where a sample of the region puts most values,
+  // one 1024-lane block per compute unit; else 16-bit counters in epochs
+  const size_t lds_win = (size_t)kWinBins * 4;
+  if (lds_win + 1024 <= P.dev.lds_per_block) {
+    int32_t* w0p = (int32_t*)(P.ws + P.L.state + offsetof(SelState, win0));
+    if (cube->dtype == TSA_F32)
+      TSA_TRACED("hist_place", P.s,
+                 hipLaunchKernelGGL(k_hist_place<0>, dim3(1), dim3(kPlaceThreads), 0, P.s, cube->data, cube->nx,
+                                    cube->ny, P.box, lo, hi, scale, nbins, w0p));
+    else
+      TSA_TRACED("hist_place", P.s,
+                 hipLaunchKernelGGL(k_hist_place<1>, dim3(1), dim3(kPlaceThreads), 0, P.s, cube->data, cube->nx,
+                                    cube->ny, P.box, lo, hi, scale, nbins, w0p));
+    int grid = P.dev.cus;
+    if (grid > P.grid) grid = P.grid;
+    int stw = TSA_OK;
+    TSA_DISPATCH(cube->dtype, P.vec, tuning().nt,
+                 stw = (launch_hist_win<DT, VEC, NT>(P, grid, lds_win, lo, hi, scale, nbins, w0p, d_counts, outl)));
+    if (stw) return stw;
     return launch_ok();
   }
   return run_histogram_wide(cube, P.g, P.vec, P.grid, P.block, lo, hi, scale, nbins, d_counts, outl, P.s);

@@ -494,6 +494,34 @@ struct HistWinAcc {
   TSA_DEV void chunk() {}
 };
 
+// HistWinAcc for a caller's range [lo, hi]: values below lo and above hi are
+// counted apart (as HistAcc counts them), in-range values in the window
+// [w0, w0 + kWinBins) go to the LDS counters, the other in-range values to
+// the global bins.
+struct HistWinOutAcc {
+  uint32_t* lds;
+  float lo, hi, scale;
+  int32_t nbm1, w0;
+  uint64_t* counts;
+  uint32_t below = 0, above = 0;
+  template <class T>
+  TSA_DEV void operator()(T raw, bool in) {
+    const float v = (float)raw;  // exact for int16
+    below += (in && v < lo) ? 1u : 0u;
+    above += (in && v > hi) ? 1u : 0u;
+    if (in && v >= lo && v <= hi) {  // NaN fails both tests
+      const float t = (v - lo) * scale;  // lo == hi: scale == 0 and t == 0
+      const int32_t b = min(max((int32_t)t, 0), nbm1);
+      const uint32_t rel = (uint32_t)(b - w0);
+      if (rel < kWinBins)
+        lds_inc(lds, rel);
+      else
+        atomicAdd((unsigned long long*)(counts + b), 1ull);
+    }
+  }
+  TSA_DEV void chunk() {}
+};
+
 // ---- histogram with 16-bit LDS counters (up to 65536 bins) ---------------------
 // Bins [b0, b0+nb) live as 16-bit halves of LDS words; every `epoch` calls of
 // chunk() the block adds its non-zero counters to the global uint64 bins and

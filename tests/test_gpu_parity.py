@@ -263,6 +263,19 @@ def test_stats_many_bins_outside_window(case):
     check_moments(res, want, dt, case)
     check_median(res["median"], want["median"], dt, case)
     check_hist(c, o, want["counts"], want["outliers"], case)
+    # the standalone call: a window placed from a sample, the rest (and the
+    # values outside a narrower range) counted apart
+    vals = host[~np.isnan(host)] if host.dtype == np.float32 else host
+    narrow = (float(np.float32(np.percentile(vals, 10))), float(np.float32(np.percentile(vals, 95))))
+    for nb in (20000, 65536):
+        for lo, hi in [(float(want["min"]), float(want["max"])), narrow]:
+            wc, wo = oracle.histogram(host, lo, hi, nb)
+            c, o = tsa.histogram(dev, lo, hi, nb)
+            check_hist(c, o, wc, wo, f"{case} histogram {nb} [{lo}, {hi}]")
+    b = (7, 5, 3, 120, 90, 37)
+    wc, wo = oracle.histogram(host, narrow[0], narrow[1], 65536, b)
+    c, o = tsa.histogram(dev, narrow[0], narrow[1], 65536, b)
+    check_hist(c, o, wc, wo, f"{case} histogram region")
 
 
 def test_stats_graph_replays_match_direct_launch():
