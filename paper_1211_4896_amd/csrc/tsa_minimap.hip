@@ -274,7 +274,13 @@ struct MMShared {
   float lo, hi, scale, shift;
   uint32_t hist_ok, var_on;
   uint32_t status;
+  uint32_t ncand;  // keys of the first-digit bucket copied to the candidate list
 };
+
+// Keys of the first-digit bucket a cell copies to LDS during the second sweep
+// (when the bucket is no larger), so the last digit is counted over them
+// instead of over every value again.
+constexpr uint32_t kMMCand = 4096;
 
 // One workgroup per cell, the cell held in registers (a 30^3 cell is 53
 // values per lane), all loaded at once, and the LDS holds only counters.  The per-value work
@@ -295,7 +301,8 @@ struct MMShared {
 template <int DT, int EPT>
 __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
   using T = typename Ty<DT>::T;
-  extern __shared__ uint32_t lds[];  // digit counters [kBins1 + kTrash] | histogram [(nbins << rshift) + kTrash]
+  // digit counters [kBins1 + kTrash] | histogram [(nbins << rshift) + kTrash] | candidates [kMMCand]
+  extern __shared__ uint32_t lds[];
   __shared__ MMShared sh;
   const int t = threadIdx.x;
   const int64_t cell = (int64_t)(blockIdx.x % 8u) * a.per_xcd + blockIdx.x / 8u;
@@ -309,6 +316,7 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
   uint32_t* dig = lds;
   uint32_t* hist = lds + kBins1 + kTrash;
   const uint32_t hwords = ((uint32_t)a.nbins << a.rshift) + kTrash;
+  uint32_t* cand = hist + hwords;
   for (uint32_t i = t; i < kBins1 + kTrash; i += kMMBlock) dig[i] = 0u;
   for (uint32_t i = t; i < hwords; i += kMMBlock) hist[i] = 0u;
 
@@ -440,7 +448,9 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
     uint32_t cum, bucket;  // a cell holds fewer than 2^32 voxels
     bool found = block_select_small(dig, kBins1, (uint32_t)sh.k, sh, &d1, &cum, &bucket);
     uint32_t k = (uint32_t)sh.k - cum;
+    const bool compact = bucket <= kMMCand;  // the bucket's keys fit the candidate list
     for (uint32_t i = t; i < kBins2; i += kMMBlock) dig[i] = 0u;
+    if (t == 0) sh.ncand = 0;
     __syncthreads();
     // histogram over [min, max] (the formula of HistOwnAcc: b = min((int)((v -
     // lo) * scale), nbins - 1), replica lane % R of bin b) + second digit
@@ -462,7 +472,14 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
           lds_inc(hrep, (uint32_t)min((int32_t)tb, nbm1) << rshift);          \
         }                                                                     \
         const uint32_t k = key_f32(__float_as_uint(v));                       \
-        if ((k >> kShift1) == d1) lds_inc(dig, (k >> kShift2) & 0xFFFu);      \
+        if ((k >> kShift1) == d1) {                                           \
+          lds_inc(dig, (k >> kShift2) & 0xFFFu);                              \
+          if (compact) {                                                      \
+            const uint32_t slot = __hip_atomic_fetch_add(                     \
+                &sh.ncand, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);  \
+            if (slot < kMMCand) cand[slot] = k;                               \
+          }                                                                   \
+        }                                                                     \
         VAR_STEP;                                                             \
       }                                                                       \
     }                                                                         \
@@ -482,6 +499,7 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
       R.m2 = m2;
       R.std = sqrt(m2 / n);
     }
+    const uint32_t ncand = min(sh.ncand, kMMCand);  // final: the sweep ended at a barrier
     found = block_select_small(dig, kBins2, k, sh, &d2, &cum, &bucket) && found;
     k -= cum;
     const uint32_t prefix = (d1 << kShift1) | (d2 << kShift2);
@@ -489,11 +507,16 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
     for (uint32_t i = t; i < kBins3; i += kMMBlock) dig[i] = 0u;
     __syncthreads();
     const uint32_t p2 = prefix >> kShift2;
+    if (compact) {  // over the bucket's copied keys
+      for (uint32_t i = t; i < ncand; i += kMMBlock) {
+        const uint32_t key = cand[i];
+        if ((key >> kShift2) == p2) lds_inc(dig, key & 0xFFu);
+      }
+    } else {  // over every value again
 #pragma unroll
-    for (int j = 0; j < EPT; ++j) asm volatile("" : "+v"(x[j]));
+      for (int j = 0; j < EPT; ++j) asm volatile("" : "+v"(x[j]));
 #pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-      {
+      for (int j = 0; j < EPT; ++j) {
         const float v = x[j];
         if (v == v) {
           const uint32_t k = key_f32(__float_as_uint(v));
@@ -571,7 +594,7 @@ int run_minimap(const tsa_cube* cube, int32_t cx, int32_t cy, int32_t cz, int32_
     // histogram replicas: up to 16 per bin within 4096 counters
     uint32_t rshift = 0;
     while (rshift < 4 && ((uint32_t)nbins << (rshift + 1)) <= 4096u) ++rshift;
-    const size_t lds = ((size_t)kBins1 + kTrash + ((size_t)nbins << rshift) + kTrash) * 4;
+    const size_t lds = ((size_t)kBins1 + kTrash + ((size_t)nbins << rshift) + kTrash + kMMCand) * 4;
     MMArgs m;
     m.base = cube->data;
     m.nx = cube->nx;
