@@ -259,6 +259,7 @@ struct MMArgs {
   int64_t ncx, ncy, ncells, per_xcd;
   uint32_t rshift, pad;
   Magic mx_full, mx_edge, my_full, my_edge;  // division by a cell's width / height (full or last cell)
+  uint32_t ky_full, ky_edge;                 // ceil(2^32 / height) of a full / the last cell (0 for height 1)
   tsa_result* out;
   uint64_t* hists;
 };
@@ -282,6 +283,36 @@ struct MMShared {
 // instead of over every value again.
 constexpr uint32_t kMMCand = 4096;
 
+// LDS words by byte address.  The per-value increments add a shifted index to
+// a base held in a register (one shift-and-add), and add a register holding 1:
+// both values pass through an empty asm barrier so the compiler neither folds
+// the base back into a constant it adds separately nor rebuilds the 1 before
+// every increment.
+typedef __attribute__((address_space(3))) uint32_t lds_word;
+TSA_DEV uint32_t lds_byte_addr(uint32_t* p) { return (uint32_t)(uintptr_t)(lds_word*)p; }
+TSA_DEV uint32_t in_register(uint32_t v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+TSA_DEV uint32_t in_scalar_register(uint32_t v) {
+  asm volatile("" : "+s"(v));
+  return v;
+}
+TSA_DEV void lds_add_at(uint32_t byte_addr, uint32_t v) {
+  __hip_atomic_fetch_add((lds_word*)(uintptr_t)byte_addr, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Histogram words of a cell: nbins << rshift replicas and the trash words,
+// rounded up to whole 16-byte groups.
+__host__ __device__ inline uint32_t mm_hist_words(int32_t nbins, uint32_t rshift) {
+  return ((((uint32_t)nbins << rshift) + kTrash) + 3u) & ~3u;
+}
+// Clears `words` (a multiple of 4) LDS words from a 16-byte aligned start, 16 bytes a store.
+TSA_DEV void mm_zero(uint32_t* p, uint32_t words, int t) {
+  uint4* q = reinterpret_cast<uint4*>(p);
+  for (uint32_t i = (uint32_t)t; i < words / 4u; i += kMMBlock) q[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
 // One workgroup per cell, the cell held in registers (a 30^3 cell is 53
 // values per lane), all loaded at once, and the LDS holds only counters.  The per-value work
 // (moments, keys, digits, histogram) bounds this kernel by VALU issue, not
@@ -302,7 +333,7 @@ template <int DT, int EPT>
 __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
   using T = typename Ty<DT>::T;
   // digit counters [kBins1 + kTrash] | histogram [(nbins << rshift) + kTrash] | candidates [kMMCand]
-  extern __shared__ uint32_t lds[];
+  extern __shared__ __align__(16) uint32_t lds[];
   __shared__ MMShared sh;
   const int t = threadIdx.x;
   const int64_t cell = (int64_t)(blockIdx.x % 8u) * a.per_xcd + blockIdx.x / 8u;
@@ -315,17 +346,21 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
   const uint32_t nvox = w * h * dd;
   uint32_t* dig = lds;
   uint32_t* hist = lds + kBins1 + kTrash;
-  const uint32_t hwords = ((uint32_t)a.nbins << a.rshift) + kTrash;
+  const uint32_t hwords = mm_hist_words(a.nbins, a.rshift);
   uint32_t* cand = hist + hwords;
-  for (uint32_t i = t; i < kBins1 + kTrash; i += kMMBlock) dig[i] = 0u;
-  for (uint32_t i = t; i < hwords; i += kMMBlock) hist[i] = 0u;
+  mm_zero(dig, kBins1 + kTrash + hwords, t);  // digit counters and histogram, adjacent
 
   // 1. every load of the lane in flight at once
   float x[EPT];
-  const T* base = (const T*)a.base + (z0 * a.nx * a.ny + y0 * a.nx + x0);
+  // the cell's corner, made visibly uniform (scalar registers) for the loads' scalar base
+  const uint64_t corner_v = (uint64_t)(uintptr_t)((const T*)a.base + (z0 * a.nx * a.ny + y0 * a.nx + x0));
+  typedef const __attribute__((address_space(1))) char gchar;
+  gchar* corner = (gchar*)(uintptr_t)(
+      ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(corner_v >> 32)) << 32) |
+      (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)corner_v));  // the builtin returns int: no sign extension
   const Magic mw = w == (uint32_t)a.cx ? a.mx_full : a.mx_edge;
   const Magic mh = h == (uint32_t)a.cy ? a.my_full : a.my_edge;
-  // a cell spans fewer than 2^31 elements of the cube (checked on the host)
+  const uint32_t kh = h == (uint32_t)a.cy ? a.ky_full : a.ky_edge;
   const uint32_t nx32 = (uint32_t)a.nx, plane32 = (uint32_t)(a.nx * a.ny);
   const uint32_t rows_side = (uint32_t)kMMBlock / w;  // w <= 512 (checked on the host)
   const uint32_t nrows = h * dd;
@@ -334,23 +369,29 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
     const uint32_t lx = (uint32_t)t - r0 * w;
     const uint32_t dz = mdiv(rows_side, mh), dy = rows_side - dz * h;  // rows_side = dz h + dy
     const uint32_t lz = mdiv(r0, mh);
-    uint32_t ly = r0 - lz * h;
-    uint32_t off = lz * plane32 + ly * nx32 + lx;
-    const uint32_t step = dz * plane32 + dy * nx32;
-    const uint32_t wrap = plane32 - h * nx32;  // y passing h: one more plane, h rows back
-    const bool lane_in = r0 < rows_side;
+    const uint32_t ly = r0 - lz * h;
+    // byte offsets from the cell's corner: a cell spans fewer than 2^32 bytes
+    // of the cube (checked on the host)
+    constexpr uint32_t es = sizeof(T);
+    uint32_t off = (lz * plane32 + ly * nx32 + lx) * es;
+    const uint32_t step = (dz * plane32 + dy * nx32) * es;
+    const uint32_t wrap = (plane32 - h * nx32) * es;  // y passing h: one more plane, h rows back
+    // y as a 32-bit fraction of h (kh = ceil(2^32 / h)): adding dy carries out
+    // of 32 bits exactly when y passes h, for the at most 2^15 rows of a cell
+    uint32_t yf = ly * kh;
+    const uint32_t dyf = dy * kh;
+    // slots holding a row of the cell: a prefix of the lane's slots
+    const uint32_t nvalid = (r0 < rows_side && r0 < nrows) ? (nrows - r0 + rows_side - 1) / rows_side : 0u;
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
-      if (lane_in && r0 + (uint32_t)j * rows_side < nrows)  // slots past the cell never touch memory
-        x[j] = (float)base[off];
+      if ((uint32_t)j < nvalid)  // slots past the cell never touch memory
+        x[j] = (float)*(const __attribute__((address_space(1))) T*)(corner + off);
       else
         x[j] = __builtin_nanf("");
-      ly += dy;
-      off += step;
-      if (ly >= h) {
-        ly -= h;
-        off += wrap;
-      }
+      uint32_t yn;
+      const bool carry = __builtin_add_overflow(yf, dyf, &yn);
+      yf = yn;
+      off += step + (carry ? wrap : 0u);
     }
   }
   __syncthreads();  // counters cleared
@@ -360,6 +401,8 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
   // digit counters need no wave vote (a wave with no matching lane skips the
   // masked LDS increment by its exec mask).
   MomAcc<0, false> mom;  // the count is the first-digit histogram's total
+  const uint32_t one = in_register(1u), dig_b = in_register(lds_byte_addr(dig));
+  const uint32_t word_shift = in_scalar_register(2u);  // kept opaque: one shift-and-add per increment
 #pragma unroll
   for (int j = 0; j < EPT; ++j) {
     {
@@ -371,7 +414,7 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
         const uint32_t k = key_f32(__float_as_uint(v));
         mom.kmin = min(mom.kmin, k);
         mom.kmax = max(mom.kmax, k);
-        lds_inc(dig, k >> kShift1);
+        lds_add_at(dig_b + ((k >> kShift1) << word_shift), one);
       }
     }
   }
@@ -449,40 +492,46 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
     bool found = block_select_small(dig, kBins1, (uint32_t)sh.k, sh, &d1, &cum, &bucket);
     uint32_t k = (uint32_t)sh.k - cum;
     const bool compact = bucket <= kMMCand;  // the bucket's keys fit the candidate list
-    for (uint32_t i = t; i < kBins2; i += kMMBlock) dig[i] = 0u;
+    mm_zero(dig, kBins2, t);
     if (t == 0) sh.ncand = 0;
     __syncthreads();
     // histogram over [min, max] (the formula of HistOwnAcc: b = min((int)((v -
-    // lo) * scale), nbins - 1), replica lane % R of bin b) + second digit
+    // lo) * scale), nbins - 1), replica lane % R of bin b) + second digit.  A
+    // cell without a histogram still counts (every index clamped into the
+    // bins, never written out), so the sweep needs no switch.
     const float lo = sh.lo, scale = sh.scale;
-    const int32_t nbm1 = a.nbins - 1;
-    const uint32_t rshift = a.rshift;
-    uint32_t* hrep = hist + ((uint32_t)t & ((1u << rshift) - 1u));
+    const uint32_t nbm1 = (uint32_t)a.nbins - 1u;
+    const uint32_t rshift = a.rshift, rs2 = rshift + 2u;
+    const uint32_t hrep_b = in_register(lds_byte_addr(hist) + (((uint32_t)t & ((1u << rshift) - 1u)) << 2));
+    // the first digit's bucket as a float interval, to its non-NaN keys; the
+    // test on floats admits both zeros at a zero end, the key then decides
+    const uint32_t kb0 = max(d1 << kShift1, 0x007FFFFFu);
+    const uint32_t kb1 = min((d1 << kShift1) | ((1u << kShift1) - 1u), 0xFF800000u);
+    const float blo = __uint_as_float(f32bits_of_key(kb0)), bhi = __uint_as_float(f32bits_of_key(kb1));
     VarAcc var{sh.shift};
-    // block-uniform switches, kept in scalar registers
-    const bool hist_on = __builtin_amdgcn_readfirstlane(sh.hist_ok) != 0;
+    // block-uniform switch, kept in a scalar register
     const bool var_on = __builtin_amdgcn_readfirstlane(sh.var_on) != 0;
-#define TSA_MM_PASS2(VAR_STEP)                                                \
-  _Pragma("unroll") for (int j = 0; j < EPT; ++j) {                           \
-    {                                                                         \
-      const float v = x[j];                                                   \
-      if (v == v) {                                                           \
-        if (hist_on) {                                                        \
-          const float tb = (v - lo) * scale; /* lo == hi: scale 0, tb 0 */    \
-          lds_inc(hrep, (uint32_t)min((int32_t)tb, nbm1) << rshift);          \
-        }                                                                     \
-        const uint32_t k = key_f32(__float_as_uint(v));                       \
-        if ((k >> kShift1) == d1) {                                           \
-          lds_inc(dig, (k >> kShift2) & 0xFFFu);                              \
-          if (compact) {                                                      \
-            const uint32_t slot = __hip_atomic_fetch_add(                     \
-                &sh.ncand, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);  \
-            if (slot < kMMCand) cand[slot] = k;                               \
-          }                                                                   \
-        }                                                                     \
-        VAR_STEP;                                                             \
-      }                                                                       \
-    }                                                                         \
+#define TSA_MM_PASS2(VAR_STEP)                                                  \
+  _Pragma("unroll") for (int j = 0; j < EPT; ++j) {                             \
+    {                                                                           \
+      const float v = x[j];                                                     \
+      if (v == v) {                                                             \
+        const float tb = (v - lo) * scale; /* lo == hi: scale 0, tb 0 */        \
+        lds_add_at(hrep_b + (min((uint32_t)(int32_t)tb, nbm1) << rs2), one);    \
+        if (v >= blo && v <= bhi) {                                             \
+          const uint32_t k = key_f32(__float_as_uint(v));                       \
+          if ((k >> kShift1) == d1) {                                           \
+            lds_inc(dig, (k >> kShift2) & 0xFFFu);                              \
+            if (compact) {                                                      \
+              const uint32_t slot = __hip_atomic_fetch_add(                     \
+                  &sh.ncand, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);  \
+              if (slot < kMMCand) cand[slot] = k;                               \
+            }                                                                   \
+          }                                                                     \
+        }                                                                       \
+        VAR_STEP;                                                               \
+      }                                                                         \
+    }                                                                           \
   }
     if (var_on)  // rare: the second moment about the mean in the same sweep
       TSA_MM_PASS2(var(v, true))
@@ -504,7 +553,7 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
     k -= cum;
     const uint32_t prefix = (d1 << kShift1) | (d2 << kShift2);
     // 3. last 8 bits over the keys of the second-digit bucket
-    for (uint32_t i = t; i < kBins3; i += kMMBlock) dig[i] = 0u;
+    mm_zero(dig, kBins3, t);
     __syncthreads();
     const uint32_t p2 = prefix >> kShift2;
     if (compact) {  // over the bucket's copied keys
@@ -536,19 +585,29 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
     }
   }
   __syncthreads();
-  // 4. the cell's histogram (every bin written)
+  // 4. the cell's histogram (every bin written).  G threads (a power of two,
+  // at most 8) share a bin, each summing R / G of its replicas in an order
+  // rotated by the bin so a wave's reads fall in different banks, and the G
+  // partial sums meet by lane exchange.
   uint64_t* H = a.hists + cell * (int64_t)a.nbins;
-  const uint32_t ok = sh.hist_ok, R1 = 1u << a.rshift;
-  for (int32_t b = t; b < a.nbins; b += kMMBlock) {
-    uint64_t c = 0;
-    if (ok == 1) {
-      for (uint32_t r = 0; r < R1; ++r) c += hist[((uint32_t)b << a.rshift) + r];
-    } else if (ok == 2 && b == 0) {
-      c = sh.cnt;
+  const uint32_t ok = sh.hist_ok, R1 = 1u << a.rshift, nb = (uint32_t)a.nbins;
+  uint32_t lg = 0;  // log2 G
+  while (lg < 3u && (1u << (lg + 1u)) <= R1 && (nb << (lg + 1u)) <= (uint32_t)kMMBlock) ++lg;
+  const uint32_t G = 1u << lg, per = R1 >> lg;
+  for (uint32_t base = 0; base < (nb << lg); base += kMMBlock) {  // the same trip count for every lane
+    const uint32_t idx = base + (uint32_t)t, b = idx >> lg, part = idx & (G - 1u);
+    uint32_t c = 0;
+    if (ok == 1u && b < nb) {
+      const uint32_t* hb = hist + (b << a.rshift) + part * per;
+      for (uint32_t i = 0; i < per; ++i) c += hb[(i + b) & (per - 1u)];
     }
-    H[b] = c;
+    for (uint32_t m = 1; m < G; m <<= 1) c += __shfl_xor(c, (int)m);
+    if (b < nb && part == 0) H[b] = ok == 1u ? (uint64_t)c : (ok == 2u && b == 0) ? sh.cnt : 0ull;
   }
 }
+
+// ceil(2^32 / h) as a 32-bit y fraction step (h = 1 never wraps: 0)
+uint32_t y_fraction(uint64_t h) { return h <= 1 ? 0u : (uint32_t)(((1ull << 32) + h - 1) / h); }
 
 // Values per lane for a w x h x d cell (0: the register path does not hold
 // it): rows of w voxels, 512 / w rows side by side.
@@ -587,14 +646,16 @@ int run_minimap(const tsa_cube* cube, int32_t cx, int32_t cy, int32_t cz, int32_
   hipStream_t s = (hipStream_t)stream;
   const uint64_t cxe = (uint64_t)(cx < cube->nx ? cx : cube->nx), cye = (uint64_t)(cy < cube->ny ? cy : cube->ny),
                  cze = (uint64_t)(cz < cube->nz ? cz : cube->nz);
-  // 32-bit offsets inside a cell: its corner to its far corner
-  const bool span32 = (double)cze * (double)cube->nx * (double)cube->ny < 2147483648.0;
+  // 32-bit byte offsets inside a cell: its corner to its far corner
+  const bool span32 = (double)cze * (double)cube->nx * (double)cube->ny * (cube->dtype == TSA_F32 ? 4.0 : 2.0) <
+                      4294967296.0;
   const int ept = span32 ? mm_ept(cxe, cye, cze) : 0;
   if (ept && register_path_on()) {
-    // histogram replicas: up to 16 per bin within 4096 counters
+    // histogram replicas: up to 64 per bin within 4096 counters (64: one per
+    // lane of a wave, so a wave's increments never share a word or a bank)
     uint32_t rshift = 0;
-    while (rshift < 4 && ((uint32_t)nbins << (rshift + 1)) <= 4096u) ++rshift;
-    const size_t lds = ((size_t)kBins1 + kTrash + ((size_t)nbins << rshift) + kTrash + kMMCand) * 4;
+    while (rshift < 6 && ((uint32_t)nbins << (rshift + 1)) <= 4096u) ++rshift;
+    const size_t lds = ((size_t)kBins1 + kTrash + mm_hist_words(nbins, rshift) + kMMCand) * 4;
     MMArgs m;
     m.base = cube->data;
     m.nx = cube->nx;
@@ -615,6 +676,8 @@ int run_minimap(const tsa_cube* cube, int32_t cx, int32_t cy, int32_t cz, int32_
     m.mx_edge = make_magic((uint32_t)ex);
     m.my_full = make_magic((uint32_t)(cy < cube->ny ? cy : cube->ny));
     m.my_edge = make_magic((uint32_t)ey);
+    m.ky_full = y_fraction((uint64_t)(cy < cube->ny ? cy : cube->ny));
+    m.ky_edge = y_fraction((uint64_t)ey);
     m.out = d_cells;
     m.hists = d_hists;
     const dim3 grid((uint32_t)(m.per_xcd * 8));

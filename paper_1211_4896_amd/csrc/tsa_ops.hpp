@@ -670,8 +670,16 @@ TSA_DEV bool block_select_small(const uint32_t* hist, int nb, uint32_t k, SH& sh
   const int per = (nb + bs - 1) / bs;
   const int b0 = t * per;
   uint32_t local = 0;
-  for (int i = 0; i < per; ++i)
-    if (b0 + i < nb) local += hist[b0 + i];
+  if ((per & (per - 1)) == 0) {  // a power of two: each run read from an offset rotated by t / 8,
+    // so lanes whose runs start in the same bank read different banks (8 a run: none shared)
+    for (int i = 0; i < per; ++i) {
+      const int j = b0 + ((i + (t >> 3)) & (per - 1));
+      if (j < nb) local += hist[j];
+    }
+  } else {
+    for (int i = 0; i < per; ++i)
+      if (b0 + i < nb) local += hist[b0 + i];
+  }
   const int lane = t % kWave, w = t / kWave;
   const uint32_t inc = wave_scan_incl_u32(local);
   if (lane == kWave - 1) sh.wsum32[w] = inc;
