@@ -3,11 +3,12 @@
 // threshold built from it: per cell, how many voxels lie above the cell's
 // mean + k standard deviations.
 //
-// Cells whose rows hold at most 512 voxels and whose 512 / w rows per lane
-// cover the cell in 64 values (a 30x30x30 cell: 53) are answered by one
-// 512-lane workgroup each, the cell read from HBM once into registers (up to
-// 64 values per lane; at most ~100 registers a lane, so two workgroups share
-// a compute unit and one's loads and barriers overlap the other's counting):
+// Cells whose rows hold at most 768 voxels and whose 768 / w rows per lane
+// cover the cell in 64 values (a 30x30x30 cell: 36) are answered by one
+// 768-lane workgroup each, the cell read from HBM once into registers (up to
+// 64 values per lane; at most 80 registers a lane up to 40 values, so two
+// workgroups share a compute unit and one's loads and barriers overlap the
+// other's counting):
 // moments and the first key digit, then the histogram
 // over the cell's own [min, max] and the other two radix digits of the median,
 // all from registers, with only the counters in LDS.  Larger cells go through
@@ -250,7 +251,7 @@ __global__ __launch_bounds__(kSigBlock) void k_sigma(SigArgs a) {
 }
 
 // ---- LDS-resident cells ----------------------------------------------------------
-constexpr int kMMBlock = 512;
+constexpr int kMMBlock = 768;
 
 struct MMArgs {
   const void* base;
@@ -313,18 +314,18 @@ TSA_DEV void mm_zero(uint32_t* p, uint32_t words, int t) {
   for (uint32_t i = (uint32_t)t; i < words / 4u; i += kMMBlock) q[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
-// One workgroup per cell, the cell held in registers (a 30^3 cell is 53
+// One workgroup per cell, the cell held in registers (a 30^3 cell is 36
 // values per lane), all loaded at once, and the LDS holds only counters.  The per-value work
 // (moments, keys, digits, histogram) bounds this kernel by VALU issue, not
 // by HBM.  Every value is held as float32: int16 converts exactly, its double
 // sums stay exact (a cell's sums of squares stay below 2^53) and float keys
 // order it the same way, and slots past the cell hold NaN, so no per-slot
-// validity test is needed.  Block b works on cell (b % 8) * per_xcd + b / 8,
+// validity test is needed past the loads.  Block b works on cell (b % 8) * per_xcd + b / 8,
 // so the cells one XCD (and its L2) sees are neighbours sharing cache lines at
 // their x edges.
 //
 // Lanes take whole rows of the cell: lane t owns column t % w, and with
-// R = 512 / w rows side by side it holds rows t / w, t / w + R, t / w + 2R,
+// R = 768 / w rows side by side it holds rows t / w, t / w + R, t / w + 2R,
 // ... of the cell's h * d rows (row r is y = r % h, z = r / h).  Each value is
 // one constant address step from the last, plus a plane carry when y wraps,
 // in 32-bit offsets from the cell's corner.  Slots past the cell (and lanes
@@ -362,7 +363,7 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
   const Magic mh = h == (uint32_t)a.cy ? a.my_full : a.my_edge;
   const uint32_t kh = h == (uint32_t)a.cy ? a.ky_full : a.ky_edge;
   const uint32_t nx32 = (uint32_t)a.nx, plane32 = (uint32_t)(a.nx * a.ny);
-  const uint32_t rows_side = (uint32_t)kMMBlock / w;  // w <= 512 (checked on the host)
+  const uint32_t rows_side = (uint32_t)kMMBlock / w;  // w <= 768 (checked on the host)
   const uint32_t nrows = h * dd;
   {
     const uint32_t r0 = mdiv((uint32_t)t, mw);
@@ -610,11 +611,11 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
 uint32_t y_fraction(uint64_t h) { return h <= 1 ? 0u : (uint32_t)(((1ull << 32) + h - 1) / h); }
 
 // Values per lane for a w x h x d cell (0: the register path does not hold
-// it): rows of w voxels, 512 / w rows side by side.
+// it): rows of w voxels, 768 / w rows side by side.
 int mm_ept(uint64_t w, uint64_t h, uint64_t d) {
   if (w > (uint64_t)kMMBlock) return 0;
   const uint64_t side = kMMBlock / w, need = (h * d + side - 1) / side;
-  for (int e : {16, 32, 48, 56, 64})
+  for (int e : {16, 32, 36, 40, 48, 64})
     if (need <= (uint64_t)e) return e;
   return 0;
 }
@@ -689,10 +690,12 @@ int run_minimap(const tsa_cube* cube, int32_t cx, int32_t cy, int32_t cz, int32_
       TSA_MM_LAUNCH(DTV, 16);      \
     else if (ept == 32)            \
       TSA_MM_LAUNCH(DTV, 32);      \
+    else if (ept == 36)            \
+      TSA_MM_LAUNCH(DTV, 36);      \
+    else if (ept == 40)            \
+      TSA_MM_LAUNCH(DTV, 40);      \
     else if (ept == 48)            \
       TSA_MM_LAUNCH(DTV, 48);      \
-    else if (ept == 56)            \
-      TSA_MM_LAUNCH(DTV, 56);      \
     else                           \
       TSA_MM_LAUNCH(DTV, 64);      \
   } while (0)

@@ -79,12 +79,14 @@ def test_minimap_ragged_cells_and_chunks():
 
 
 def test_minimap_register_sizes():
-    """Cells filling each register layout: up to 16, 32, 48, 56 and 64 values per lane
-    (512 lanes), in both the plane layout (16^3, 32x16x30) and the row layout."""
+    """Cells filling each register layout of the 768-lane workgroup: up to 16, 32, 36,
+    40, 48 and 64 values per lane (16^3, 32x16x30, 30^3, 32x16x60, 32^3, 32x32x48),
+    plus a one-plane cell and a 40x25x20 cell."""
     rng = np.random.default_rng(13)
     host = (rng.standard_normal((64, 60, 100)) * 3 + 1).astype(np.float32)
     host[10, 5:9, :] = np.nan
-    for cell in ((16, 16, 16), (32, 16, 30), (32, 16, 60), (100, 60, 1), (40, 25, 20), (30, 30, 30), (32, 32, 32)):
+    for cell in ((16, 16, 16), (32, 16, 30), (30, 30, 30), (32, 16, 60), (32, 32, 32), (32, 32, 48), (100, 60, 1),
+                 (40, 25, 20)):
         _run(host, cell, 16, (2.0,), f"cells {cell}")
 
 
