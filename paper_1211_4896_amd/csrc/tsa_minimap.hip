@@ -261,6 +261,7 @@ struct MMArgs {
   uint32_t rshift, pad;
   Magic mx_full, mx_edge, my_full, my_edge;  // division by a cell's width / height (full or last cell)
   uint32_t ky_full, ky_edge;                 // ceil(2^32 / height) of a full / the last cell (0 for height 1)
+  Magic m_ncx, m_ncy;                        // division by the grid's cells along x and y
   tsa_result* out;
   uint64_t* hists;
 };
@@ -330,8 +331,11 @@ TSA_DEV void mm_zero(uint32_t* p, uint32_t words, int t) {
 // one constant address step from the last, plus a plane carry when y wraps,
 // in 32-bit offsets from the cell's corner.  Slots past the cell (and lanes
 // past R whole rows) hold NaN and drop out at each step's NaN test.
+// Up to 40 values a lane the kernel is held to 80 registers, so two
+// workgroups (six waves a SIMD) share a compute unit.
 template <int DT, int EPT>
-__global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
+__global__ __launch_bounds__(kMMBlock) __attribute__((amdgpu_waves_per_eu(EPT <= 40 ? 6 : 3))) void k_mm_reg(
+    MMArgs a) {
   using T = typename Ty<DT>::T;
   // digit counters [kBins1 + kTrash] | histogram [(nbins << rshift) + kTrash] | candidates [kMMCand]
   extern __shared__ __align__(16) uint32_t lds[];
@@ -339,7 +343,10 @@ __global__ __launch_bounds__(kMMBlock) void k_mm_reg(MMArgs a) {
   const int t = threadIdx.x;
   const int64_t cell = (int64_t)(blockIdx.x % 8u) * a.per_xcd + blockIdx.x / 8u;
   if (cell >= a.ncells) return;  // the same for the whole block
-  const int64_t ci = cell % a.ncx, cj = (cell / a.ncx) % a.ncy, ck = cell / (a.ncx * a.ncy);
+  // the grid holds fewer than 2^31 cells (checked on the host): 32-bit
+  // divisions by multiply-high, not 64-bit divisions in every wave
+  const uint32_t c32 = (uint32_t)cell, row = mdiv(c32, a.m_ncx), ck32 = mdiv(row, a.m_ncy);
+  const int64_t ci = c32 - row * (uint32_t)a.ncx, cj = row - ck32 * (uint32_t)a.ncy, ck = ck32;
   const int64_t x0 = ci * a.cx, y0 = cj * a.cy, z0 = ck * a.cz;
   const uint32_t w = (uint32_t)(min(x0 + (int64_t)a.cx, a.nx) - x0);
   const uint32_t h = (uint32_t)(min(y0 + (int64_t)a.cy, a.ny) - y0);
@@ -650,7 +657,7 @@ int run_minimap(const tsa_cube* cube, int32_t cx, int32_t cy, int32_t cz, int32_
   // 32-bit byte offsets inside a cell: its corner to its far corner
   const bool span32 = (double)cze * (double)cube->nx * (double)cube->ny * (cube->dtype == TSA_F32 ? 4.0 : 2.0) <
                       4294967296.0;
-  const int ept = span32 ? mm_ept(cxe, cye, cze) : 0;
+  const int ept = (span32 && g.ncells < (1ll << 31)) ? mm_ept(cxe, cye, cze) : 0;
   if (ept && register_path_on()) {
     // histogram replicas: up to 64 per bin within 4096 counters (64: one per
     // lane of a wave, so a wave's increments never share a word or a bank)
@@ -677,6 +684,8 @@ int run_minimap(const tsa_cube* cube, int32_t cx, int32_t cy, int32_t cz, int32_
     m.mx_edge = make_magic((uint32_t)ex);
     m.my_full = make_magic((uint32_t)(cy < cube->ny ? cy : cube->ny));
     m.my_edge = make_magic((uint32_t)ey);
+    m.m_ncx = make_magic((uint32_t)g.ncx);
+    m.m_ncy = make_magic((uint32_t)g.ncy);
     m.ky_full = y_fraction((uint64_t)(cy < cube->ny ? cy : cube->ny));
     m.ky_edge = y_fraction((uint64_t)ey);
     m.out = d_cells;
