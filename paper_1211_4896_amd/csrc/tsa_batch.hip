@@ -978,7 +978,7 @@ uint32_t batch_rep_shift(int32_t nbins, int replicas, size_t lds_per_cu, int bpc
                              : (uint32_t)__builtin_ctz((unsigned)replicas);
   size_t cap = lds_per_cu / (size_t)(bpc > 0 ? bpc : 1);
   if (cap > 65536) cap = 65536;
-  cap = cap > 2048 ? cap - 2048 : 0;  // the kernel's static LDS
+  cap = cap > 4096 ? cap - 4096 : 0;  // the kernel's static LDS (about 3.2 KB)
   while (r > 0 && ((((size_t)nbins << r) + kTrash + kBins2) * 4) > cap) --r;
   return r;
 }

@@ -807,10 +807,30 @@ TSA_DEV void cand_append(bool m, uint32_t key, CandSink& k) {
   if (bal != 0) cand_append_slow(m, key, bal, k);
 }
 
-// Whole wave: copy out what is still staged.
-TSA_DEV void cand_finish(CandSink& k) {
-  if (k.fill) cand_copy_out(k, k.fill);
+// Whole block (blockDim.x at most 1024): every wave's still-staged keys
+// copied out under one global reservation for the block.  One same-address
+// atomic per block instead of one per wave: when a thousand blocks end
+// together (a small cube, one unit of work each) their waves' reservations
+// queued on the one counter for tens of microseconds.
+TSA_DEV void cand_finish_block(CandSink& k) {
+  __shared__ uint32_t fill_w[16];
+  __shared__ uint32_t base_b;
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int nw = (blockDim.x + kWave - 1) / kWave;
+  if (lane == 0) fill_w[w] = k.fill;
+  __syncthreads();  // also orders every lane's staged writes before the copy
+  if (threadIdx.x == 0) {
+    uint32_t tot = 0;
+    for (int i = 0; i < nw; ++i) tot += fill_w[i];
+    base_b = tot ? atomicAdd(k.counter, tot) : 0u;
+  }
+  __syncthreads();
+  uint32_t g = base_b;
+  for (int i = 0; i < w; ++i) g += fill_w[i];
+  for (uint32_t i = lane; i < k.fill; i += kWave)
+    if (g + i < k.cap) k.list[g + i] = k.buf[w * k.stage + i];
   k.fill = 0;
+  __syncthreads();  // fill_w and base_b read by every wave before a later call rewrites them
 }
 
 template <int DT>
@@ -830,9 +850,10 @@ struct Level2Acc {  // keys inside the level-1 bucket: next 12 bits, optional co
     }
   }
   TSA_DEV void chunk() {}
-  // every wave copies what it still holds (call with every lane active)
+  // what every wave still holds, one reservation for the block (call with
+  // every thread of the block; compact is the same across the block)
   TSA_DEV void finish() {
-    if (compact) cand_finish(sink);
+    if (compact) cand_finish_block(sink);
   }
 };
 
