@@ -256,7 +256,7 @@ struct BShared {
   uint32_t cand_base, compact;
   Partial part;
   MomShared mom;
-  uint32_t wsum32[16];
+  alignas(16) uint32_t wsum32[16];
   uint32_t found, sel_digit, sel_cum32, sel_bucket32;
 };
 

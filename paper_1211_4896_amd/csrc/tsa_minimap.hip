@@ -269,7 +269,7 @@ struct MMArgs {
 struct MMShared {
   MomShared mom;
   Partial part;
-  uint32_t wsum32[16];
+  alignas(16) uint32_t wsum32[16];
   uint32_t found, sel_digit, sel_cum32, sel_bucket32;
   // the cell's parameters, set by thread 0
   uint64_t cnt, k;

@@ -661,7 +661,7 @@ TSA_DEV uint32_t wave_scan_incl_u32(uint32_t v) {
 
 // block_select_u32 for histograms whose total fits in 32 bits (a mini-map
 // cell): 32-bit DPP scans instead of 64-bit shuffles, and every wave total
-// read at once.  SH provides wsum32[16], found, sel_digit, sel_cum32 and
+// read at once.  SH provides wsum32[16] (16-byte aligned), found, sel_digit, sel_cum32 and
 // sel_bucket32 in LDS; blockDim.x is at most 1024.
 template <class SH>
 TSA_DEV bool block_select_small(const uint32_t* hist, int nb, uint32_t k, SH& sh, uint32_t* digit,
@@ -686,8 +686,13 @@ TSA_DEV bool block_select_small(const uint32_t* hist, int nb, uint32_t k, SH& sh
   if (t == 0) sh.found = 0;
   __syncthreads();
   uint32_t base = inc - local;
+  const uint4* ws4 = reinterpret_cast<const uint4*>(sh.wsum32);  // 16-byte aligned in SH
 #pragma unroll
-  for (int i = 0; i < 16; ++i) base += (i < w) ? sh.wsum32[i] : 0u;  // waves below this one
+  for (int i = 0; i < 4; ++i) {  // waves below this one, four totals a read
+    const uint4 v = ws4[i];
+    base += (4 * i < w ? v.x : 0u) + (4 * i + 1 < w ? v.y : 0u) + (4 * i + 2 < w ? v.z : 0u) +
+            (4 * i + 3 < w ? v.w : 0u);
+  }
   if (local > 0 && k >= base && k - base < local) {
     uint32_t cum = base;
     int d = b0;
