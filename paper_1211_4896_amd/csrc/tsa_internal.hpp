@@ -18,6 +18,13 @@ namespace tsa {
 constexpr int kUnroll = 4;            // 16-byte loads in flight per lane
 constexpr uint32_t kTileUnits = 8192; // vectors per rows tile (single-region calls)
 constexpr int kMaxBlocks = 8192;      // upper bound of a pass grid (moment partial slots)
+// The fused passes add their per-block counts into kHistCopies copies of a
+// histogram (block b into copy b % kHistCopies), summed by the next one-block
+// kernel: a thousand blocks ending together otherwise queue on the same
+// counters.  Pass B's copies hold up to kCopyBinsMax bins (more bins take the
+// wide passes, which count into the output directly).
+constexpr int kHistCopies = 8;
+constexpr uint32_t kCopyBinsMax = 12288;
 // region batch: largest first-digit bucket whose keys a box copies out (larger ones
 // take a third pass over the box); the epilogue scans the copy with one block
 constexpr uint32_t kBatchCandMax = 1u << 20;

@@ -522,9 +522,12 @@ struct PassA {
 
 template <int DT, bool VEC, bool NT>
 __global__ __launch_bounds__(1024) void k_pass_a(Geom g, uint32_t rshift, Partial* __restrict__ parts,
-                                                 uint64_t* __restrict__ hist1) {
+                                                 uint64_t* __restrict__ hist1, uint64_t* __restrict__ hcopy,
+                                                 uint32_t hcopy_n) {
   extern __shared__ uint32_t lds[];
   __shared__ MomShared sm;
+  // pass B's histogram copies start at zero (cleared here, not by a launch of their own)
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < hcopy_n; i += gridDim.x * blockDim.x) hcopy[i] = 0ull;
   lds_zero(lds, ((uint32_t)kBins1 << rshift) + kTrash);
   __syncthreads();
   PassA<DT> a{MomAcc<DT, false>{}, Digit1Acc<DT>{lds, rshift, threadIdx.x & ((1u << rshift) - 1u)}};
@@ -537,14 +540,27 @@ __global__ __launch_bounds__(1024) void k_pass_a(Geom g, uint32_t rshift, Partia
   a.mom.cnt = c;
   block_store_partial(a.mom, sm, parts + blockIdx.x);
   __syncthreads();
-  lds_flush(lds, kBins1, rshift, hist1);
+  lds_flush(lds, kBins1, rshift, hist1 + (size_t)(blockIdx.x % kHistCopies) * kBins1);
 }
 
 __global__ __launch_bounds__(1024) void k_mid(const Partial* __restrict__ parts, int np, int dtype, uint64_t volume,
-                                              int32_t nbins, const uint64_t* __restrict__ hist1, SelState* st,
+                                              int32_t nbins, uint64_t* __restrict__ hist1, SelState* st,
                                               tsa_result* out) {
   __shared__ MergeShared msm;
   __shared__ SelectShared ssm;
+  // pass A's blocks added into kHistCopies copies of the first-digit counts: summed into the first
+  static_assert(kBins1 % 1024 == 0, "k_mid runs as one block of 1024 threads, four bins a thread");
+  uint64_t c[kBins1 / 1024];
+#pragma unroll
+  for (int j = 0; j < kBins1 / 1024; ++j) {  // every load issued before the first add
+    const uint32_t b = threadIdx.x + 1024u * j;
+    c[j] = hist1[b];
+#pragma unroll
+    for (int k = 1; k < kHistCopies; ++k) c[j] += hist1[(size_t)k * kBins1 + b];
+  }
+#pragma unroll
+  for (int j = 0; j < kBins1 / 1024; ++j) hist1[threadIdx.x + 1024u * j] = c[j];
+  __syncthreads();
   uint64_t n;
   uint32_t kmin, kmax;
   merge_moments(parts, np, dtype, volume, out, msm, n, kmin, kmax);
@@ -641,7 +657,8 @@ __global__ __launch_bounds__(1024) void k_pass_b(Geom g, int32_t nbins, uint32_t
   walk<DT, VEC, kUnroll, NT>(g, b);
   b.l2.finish();
   __syncthreads();
-  if (hist_on) lds_flush(lds, (uint32_t)nbins, rshift, counts);
+  // into one of kHistCopies copies (counts holds them nbins apart), summed by k_var_finish
+  if (hist_on) lds_flush(lds, (uint32_t)nbins, rshift, counts + (size_t)(blockIdx.x % kHistCopies) * (uint32_t)nbins);
   if (sel_on) lds_flush(l2, kBins2, 0, hist2);
   // values lie in their own [min, max]: the outlier counters keep their zeros
 
@@ -755,8 +772,18 @@ __global__ __launch_bounds__(1024) void k_pass_b16(Geom g, int32_t nbins, uint32
 // M2 about the shift c: M2 = sum (x-c)^2 - n (mean - c)^2, block partials
 // added in a fixed order (strided per thread, then a pairwise tree).
 __global__ __launch_bounds__(1024) void k_var_finish(const Partial* __restrict__ parts2, int np,
-                                                     const SelState* __restrict__ st, tsa_result* out) {
+                                                     const SelState* __restrict__ st, tsa_result* out,
+                                                     const uint64_t* __restrict__ hcopy, int32_t nbins,
+                                                     uint64_t* __restrict__ counts) {
   __shared__ double sq[1024];
+  if (hcopy) {  // the histogram from pass B's kHistCopies copies
+    for (uint32_t b = threadIdx.x; b < (uint32_t)nbins; b += blockDim.x) {
+      uint64_t c = 0;
+#pragma unroll
+      for (int k = 0; k < kHistCopies; ++k) c += hcopy[(size_t)k * (uint32_t)nbins + b];
+      counts[b] = c;
+    }
+  }
   if (!st->var_on) return;
   const int t = threadIdx.x, bs = blockDim.x;
   double q = 0.0;
@@ -930,7 +957,7 @@ static int pass_grid(const Geom& g, bool vec, int block, int maxblocks) {
 
 // Workspace layout of the single-region calls.
 struct WsLayout {
-  size_t partials, partials2, hist1, hist2, hist3, state, state2, result, outl, cand, total;
+  size_t partials, partials2, hist1, hist2, hist3, state, state2, result, outl, hcopy, cand, total;
   uint32_t cand_cap;
 };
 
@@ -946,7 +973,7 @@ static WsLayout ws_layout(int64_t volume, int64_t cand_limit = INT64_MAX) {
   L.partials2 = o;
   o = align256(o + sizeof(Partial) * kMaxBlocks);
   L.hist1 = o;
-  o = align256(o + 8 * kBins1);
+  o = align256(o + 8 * (size_t)kBins1 * kHistCopies);
   L.hist2 = o;
   o = align256(o + 8 * kBins2);
   L.hist3 = o;
@@ -959,6 +986,8 @@ static WsLayout ws_layout(int64_t volume, int64_t cand_limit = INT64_MAX) {
   o = align256(o + sizeof(tsa_result));
   L.outl = o;
   o = align256(o + 16);
+  L.hcopy = o;
+  o = align256(o + 8 * (size_t)kHistCopies * kCopyBinsMax);
   int64_t cap = volume / 64;
   if (cap < 65536) cap = 65536;
   if (cap > (1ll << 26)) cap = 1ll << 26;
@@ -1463,14 +1492,16 @@ static int enqueue_stats(const tsa_cube* cube, const tsa_region* region, int32_t
   uint64_t* h1 = (uint64_t*)(P.ws + P.L.hist1);
   uint64_t* h2 = (uint64_t*)(P.ws + P.L.hist2);
   uint32_t* cand = (uint32_t*)(P.ws + P.L.cand);
+  uint64_t* hcopy = (uint64_t*)(P.ws + P.L.hcopy);
+  if (!wide && nbins > (int32_t)kCopyBinsMax) return TSA_ENOTSUP;  // cannot happen: the LDS bounds nbins first
   const uint32_t rs1 = rep_shift_for(kBins1, 32768);
   TSA_TRACED("pass_a", P.s,
     TSA_DISPATCH(cube->dtype, P.vec, tuning().nt,
                  hipLaunchKernelGGL((k_pass_a<DT, VEC, NT>), dim3(P.grid), dim3(P.block), (((size_t)kBins1 << rs1) + kTrash) * 4,
-                                    P.s, P.g, rs1, parts, h1)));
+                                    P.s, P.g, rs1, parts, h1, hcopy, wide ? 0u : (uint32_t)kHistCopies * (uint32_t)nbins)));
   TSA_TRACED("mid", P.s,
              hipLaunchKernelGGL(k_mid, dim3(1), dim3(1024), 0, P.s, (const Partial*)parts, P.grid, cube->dtype,
-                                (uint64_t)P.volume, nbins, (const uint64_t*)h1, stp, d_out));
+                                (uint64_t)P.volume, nbins, h1, stp, d_out));
   Partial* parts2 = (Partial*)(P.ws + P.L.partials2);
   int np2 = P.grid;
   if (!wide) {
@@ -1494,7 +1525,7 @@ static int enqueue_stats(const tsa_cube* cube, const tsa_region* region, int32_t
     TSA_TRACED("pass_b", P.s,
       TSA_DISPATCH(cube->dtype, P.vec, tuning().nt,
                    hipLaunchKernelGGL((k_pass_b<DT, VEC, NT>), dim3(P.grid), dim3(P.block), ldsb, P.s, P.g, nbins,
-                                      rsb, stage, stp, d_counts, outl, h2, cand, parts2)));
+                                      rsb, stage, stp, hcopy, outl, h2, cand, parts2)));
   } else {
     // one 1024-thread block per compute unit: a window of 32-bit counters when
     // the device grants the LDS, else 16-bit counters flushed in epochs
@@ -1511,7 +1542,7 @@ static int enqueue_stats(const tsa_cube* cube, const tsa_region* region, int32_t
       if (stw) return stw;
       TSA_TRACED("var_finish", P.s,
                  hipLaunchKernelGGL(k_var_finish, dim3(1), dim3(1024), 0, P.s, (const Partial*)parts2, np2,
-                                    (const SelState*)stp, d_out));
+                                    (const SelState*)stp, d_out, (const uint64_t*)nullptr, nbins, d_counts));
       return launch_median_tail(cube, P, d_out, false);
     }
     const int epv = P.vec ? (cube->dtype == TSA_F32 ? 4 : 8) : 1;
@@ -1525,7 +1556,8 @@ static int enqueue_stats(const tsa_cube* cube, const tsa_region* region, int32_t
   }
   TSA_TRACED("var_finish", P.s,
              hipLaunchKernelGGL(k_var_finish, dim3(1), dim3(1024), 0, P.s, (const Partial*)parts2, np2,
-                                (const SelState*)stp, d_out));
+                                (const SelState*)stp, d_out, wide ? (const uint64_t*)nullptr : (const uint64_t*)hcopy,
+                                nbins, d_counts));
   return launch_median_tail(cube, P, d_out, false);
 }
 
