@@ -290,7 +290,8 @@ def main():
     if dev is not None and dev.numel() == synth.SPECS["c2"].n:
         api = tsa.capi()
         if not args.no_minimap:
-            line["minimap"] = _minimap_bench(tsa, torch, api, lib, dev, sh, args.region_reps)
+            # 2 ms calls: 20 of them, so one slow call does not move the mean much
+            line["minimap"] = _minimap_bench(tsa, torch, api, lib, dev, sh, max(args.region_reps, 20))
         if not args.no_spectrum:
             line["spectrum"] = _spectrum_bench(tsa, torch, np, synth, api, lib, dev, sh, args.region_reps)
     dev = None
