@@ -284,6 +284,9 @@ struct MMShared {
 // (when the bucket is no larger), so the last digit is counted over them
 // instead of over every value again.
 constexpr uint32_t kMMCand = 4096;
+// A bucket of at most kMMRankMax keys is finished from the candidate list by
+// counting ranks (no second-digit counters, no further block-wide scans).
+constexpr uint32_t kMMRankMax = 64;
 
 // LDS words by byte address.  The per-value increments add a shifted index to
 // a base held in a register (one shift-and-add), and add a register holding 1:
@@ -499,9 +502,13 @@ __global__ __launch_bounds__(kMMBlock) __attribute__((amdgpu_waves_per_eu(EPT <=
     uint32_t cum, bucket;  // a cell holds fewer than 2^32 voxels
     bool found = block_select_small(dig, kBins1, (uint32_t)sh.k, sh, &d1, &cum, &bucket);
     uint32_t k = (uint32_t)sh.k - cum;
-    const bool compact = bucket <= kMMCand;  // the bucket's keys fit the candidate list
+    const bool compact = bucket <= kMMCand;     // the bucket's keys fit the candidate list
+    const bool by_rank = bucket <= kMMRankMax;  // and are few enough to rank by counting
     mm_zero(dig, kBins2, t);
-    if (t == 0) sh.ncand = 0;
+    if (t == 0) {
+      sh.ncand = 0;
+      sh.found = 0;
+    }
     __syncthreads();
     // histogram over [min, max] (the formula of HistOwnAcc: b = min((int)((v -
     // lo) * scale), nbins - 1), replica lane % R of bin b) + second digit.  A
@@ -529,7 +536,7 @@ __global__ __launch_bounds__(kMMBlock) __attribute__((amdgpu_waves_per_eu(EPT <=
         if (v >= blo && v <= bhi) {                                             \
           const uint32_t k = key_f32(__float_as_uint(v));                       \
           if ((k >> kShift1) == d1) {                                           \
-            lds_inc(dig, (k >> kShift2) & 0xFFFu);                              \
+            if (!by_rank) lds_inc(dig, (k >> kShift2) & 0xFFFu);                \
             if (compact) {                                                      \
               const uint32_t slot = __hip_atomic_fetch_add(                     \
                   &sh.ncand, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);  \
@@ -557,38 +564,69 @@ __global__ __launch_bounds__(kMMBlock) __attribute__((amdgpu_waves_per_eu(EPT <=
       R.std = sqrt(m2 / n);
     }
     const uint32_t ncand = min(sh.ncand, kMMCand);  // final: the sweep ended at a barrier
-    found = block_select_small(dig, kBins2, k, sh, &d2, &cum, &bucket) && found;
-    k -= cum;
-    const uint32_t prefix = (d1 << kShift1) | (d2 << kShift2);
-    // 3. last 8 bits over the keys of the second-digit bucket
-    mm_zero(dig, kBins3, t);
-    __syncthreads();
-    const uint32_t p2 = prefix >> kShift2;
-    if (compact) {  // over the bucket's copied keys
-      for (uint32_t i = t; i < ncand; i += kMMBlock) {
-        const uint32_t key = cand[i];
-        if ((key >> kShift2) == p2) lds_inc(dig, key & 0xFFu);
-      }
-    } else {  // over every value again
+    if (by_rank) {
+      // 2b. the bucket's keys are all in the list: candidate i's rank is the
+      // number of keys below it plus the equal keys listed before it, so the
+      // ranks are 0..n-1 once each and one thread holds rank k
+      if ((uint32_t)t < ncand && ncand == bucket) {
+        const uint32_t key_i = cand[t];
+        const uint4* c4 = reinterpret_cast<const uint4*>(cand);  // 16-byte aligned
+        uint32_t r = 0;
+        for (uint32_t j = 0; j < ncand; j += 4) {  // every lane reads the same words
+          const uint4 q = c4[j >> 2];
+          const uint32_t kj[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
-      for (int j = 0; j < EPT; ++j) asm volatile("" : "+v"(x[j]));
-#pragma unroll
-      for (int j = 0; j < EPT; ++j) {
-        const float v = x[j];
-        if (v == v) {
-          const uint32_t k = key_f32(__float_as_uint(v));
-          if ((k >> kShift2) == p2) lds_inc(dig, k & 0xFFu);
+          for (uint32_t u = 0; u < 4; ++u)
+            r += (j + u < ncand && (kj[u] < key_i || (kj[u] == key_i && j + u < (uint32_t)t))) ? 1u : 0u;
+        }
+        if (r == k) {
+          sh.prefix = key_i;
+          sh.found = 1;
         }
       }
-    }
-    __syncthreads();
-    found = block_select_small(dig, kBins3, k, sh, &d3, &cum, &bucket) && found;
-    if (t == 0) {
-      if (found)
-        R.median = bvalue_of_key(prefix | d3, 0);
-      else {
-        R.median = __builtin_nan("");
-        R.status = TSA_EDEVICE;
+      __syncthreads();
+      if (t == 0) {
+        if (found && sh.found)
+          R.median = bvalue_of_key(sh.prefix, 0);
+        else {
+          R.median = __builtin_nan("");
+          R.status = TSA_EDEVICE;
+        }
+      }
+    } else {
+      found = block_select_small(dig, kBins2, k, sh, &d2, &cum, &bucket) && found;
+      k -= cum;
+      const uint32_t prefix = (d1 << kShift1) | (d2 << kShift2);
+      // 3. last 8 bits over the keys of the second-digit bucket
+      mm_zero(dig, kBins3, t);
+      __syncthreads();
+      const uint32_t p2 = prefix >> kShift2;
+      if (compact) {  // over the bucket's copied keys
+        for (uint32_t i = t; i < ncand; i += kMMBlock) {
+          const uint32_t key = cand[i];
+          if ((key >> kShift2) == p2) lds_inc(dig, key & 0xFFu);
+        }
+      } else {  // over every value again
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) asm volatile("" : "+v"(x[j]));
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+          const float v = x[j];
+          if (v == v) {
+            const uint32_t k = key_f32(__float_as_uint(v));
+            if ((k >> kShift2) == p2) lds_inc(dig, k & 0xFFu);
+          }
+        }
+      }
+      __syncthreads();
+      found = block_select_small(dig, kBins3, k, sh, &d3, &cum, &bucket) && found;
+      if (t == 0) {
+        if (found)
+          R.median = bvalue_of_key(prefix | d3, 0);
+        else {
+          R.median = __builtin_nan("");
+          R.status = TSA_EDEVICE;
+        }
       }
     }
   }

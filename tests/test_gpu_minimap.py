@@ -111,6 +111,9 @@ def test_minimap_degenerate_cells_and_ties():
     host[1, :5, :] = np.nan  # cells that are all NaN
     host[2, :5, :] = np.inf  # constant +inf cells: no histogram
     host[3, 5:, :] = -np.inf
+    # signed zeros and denormals: the first-digit bucket's float bounds meet at
+    # zero, where the key (-0 < +0) decides; small buckets are ranked by counting
+    host[4] = rng.choice(np.array([-0.0, 0.0, 1e-40, -1e-40, 3e-39], dtype=np.float32), (10, 12))
     _run(host, (12, 5, 1), 8, (0.0, 1.0, -1.0), "planes")
     _run(host, (1, 1, 8), 4, (0.5,), "columns")
 
