@@ -10,8 +10,9 @@
 // workgroups share a compute unit and one's loads and barriers overlap the
 // other's counting):
 // moments and the first key digit, then the histogram
-// over the cell's own [min, max] and the other two radix digits of the median,
-// all from registers, with only the counters in LDS.  Larger cells go through
+// over the cell's own [min, max] with the first digit's bucket copied to LDS,
+// and the median's last two digits (or, for a bucket of at most 64 keys, the
+// ranks of its keys), all from registers, with only counters and that copy in LDS.  Larger cells go through
 // the region batch over the grid's boxes (planned on the device, so no box
 // list crosses PCIe).  The threshold pass streams the
 // cube once in row order: a block owns a band of rows that share one cell row
@@ -320,8 +321,8 @@ TSA_DEV void mm_zero(uint32_t* p, uint32_t words, int t) {
 
 // One workgroup per cell, the cell held in registers (a 30^3 cell is 36
 // values per lane), all loaded at once, and the LDS holds only counters.  The per-value work
-// (moments, keys, digits, histogram) bounds this kernel by VALU issue, not
-// by HBM.  Every value is held as float32: int16 converts exactly, its double
+// (moments, keys, digits, histogram: two LDS atomics a value) and the per-cell
+// scans and barriers bound this kernel, not HBM.  Every value is held as float32: int16 converts exactly, its double
 // sums stay exact (a cell's sums of squares stay below 2^53) and float keys
 // order it the same way, and slots past the cell hold NaN, so no per-slot
 // validity test is needed past the loads.  Block b works on cell (b % 8) * per_xcd + b / 8,
@@ -388,7 +389,8 @@ __global__ __launch_bounds__(kMMBlock) __attribute__((amdgpu_waves_per_eu(EPT <=
     const uint32_t step = (dz * plane32 + dy * nx32) * es;
     const uint32_t wrap = (plane32 - h * nx32) * es;  // y passing h: one more plane, h rows back
     // y as a 32-bit fraction of h (kh = ceil(2^32 / h)): adding dy carries out
-    // of 32 bits exactly when y passes h, for the at most 2^15 rows of a cell
+    // of 32 bits exactly when y passes h, for the at most 64 * 768 rows of a
+    // register cell (the error of the rounded step stays below one row)
     uint32_t yf = ly * kh;
     const uint32_t dyf = dy * kh;
     // slots holding a row of the cell: a prefix of the lane's slots
@@ -511,9 +513,10 @@ __global__ __launch_bounds__(kMMBlock) __attribute__((amdgpu_waves_per_eu(EPT <=
     }
     __syncthreads();
     // histogram over [min, max] (the formula of HistOwnAcc: b = min((int)((v -
-    // lo) * scale), nbins - 1), replica lane % R of bin b) + second digit.  A
-    // cell without a histogram still counts (every index clamped into the
-    // bins, never written out), so the sweep needs no switch.
+    // lo) * scale), nbins - 1), replica lane % R of bin b) + the first digit's
+    // bucket: copied to LDS, and its second digit counted unless it is small
+    // enough to rank.  A cell without a histogram still counts (every index
+    // clamped into the bins, never written out), so the sweep needs no switch.
     const float lo = sh.lo, scale = sh.scale;
     const uint32_t nbm1 = (uint32_t)a.nbins - 1u;
     const uint32_t rshift = a.rshift, rs2 = rshift + 2u;
