@@ -17,6 +17,24 @@ __global__ void k_fill32(uint32_t* __restrict__ p, uint64_t n, uint32_t v) {
     p[i] = v;
 }
 
+// Several disjoint ranges filled by one launch: on a small cube the gaps
+// between dependent launches, not the bytes, set the time of the clears.
+struct FillRange {
+  uint32_t* p;
+  uint64_t n;
+  uint32_t v, pad;
+};
+constexpr int kMaxFills = 6;
+struct FillSet {
+  FillRange r[kMaxFills];
+  int count, pad;
+};
+__global__ void k_fill_set(FillSet f) {
+  const uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (uint64_t)gridDim.x * blockDim.x;
+  for (int k = 0; k < f.count; ++k)
+    for (uint64_t i = i0; i < f.r[k].n; i += stride) f.r[k].p[i] = f.r[k].v;
+}
+
 // ---------------------------------------------------------------------------
 // moments pass: one Partial per block
 // ---------------------------------------------------------------------------
@@ -1011,6 +1029,21 @@ static void fill32(void* p, size_t words, uint32_t v, hipStream_t s) {
   TSA_TRACED("fill", s, hipLaunchKernelGGL(k_fill32, dim3(blocks), dim3(256), 0, s, (uint32_t*)p, (uint64_t)words, v));
 }
 
+// One launch for up to kMaxFills disjoint (words, value) ranges.
+static void fill_set(std::initializer_list<FillRange> ranges, hipStream_t s) {
+  FillSet f{};
+  uint64_t most = 0;
+  for (const FillRange& r : ranges) {
+    if (r.n == 0) continue;
+    f.r[f.count++] = r;  // callers pass at most kMaxFills
+    if (r.n > most) most = r.n;
+  }
+  if (f.count == 0) return;
+  int blocks = (int)((most + 255) / 256);
+  if (blocks > 1024) blocks = 1024;
+  TSA_TRACED("fill", s, hipLaunchKernelGGL(k_fill_set, dim3(blocks), dim3(256), 0, s, f));
+}
+
 #define TSA_DISPATCH(DTV, VECV, NTV, EXPR)                              \
   do {                                                                  \
     if ((DTV) == 0 && (VECV) && (NTV)) {                                \
@@ -1089,11 +1122,20 @@ static uint32_t rep_shift_for(int nbins, size_t lds_budget) {
   return r;
 }
 
-// Zero the level histograms and the selection state, then set the capacity.
-static void reset_select(const Prep& P) {
-  fill32(P.ws + P.L.hist1, (P.L.state + sizeof(SelState) - P.L.hist1) / 4, 0u, P.s);
-  // cand_cap is set by a one-element fill at its offset
-  fill32(P.ws + P.L.state + offsetof(SelState, cand_cap), 1, P.L.cand_cap, P.s);
+// Zero the level histograms and the selection state, set the capacity, and
+// clear the caller's output counters (d_counts: nbins u64, outl: 2 u64; null
+// for none), all in one launch.
+static void reset_select(const Prep& P, uint64_t* d_counts = nullptr, int32_t nbins = 0, uint64_t* outl = nullptr) {
+  char* lo = P.ws + P.L.hist1;
+  char* cap = P.ws + P.L.state + offsetof(SelState, cand_cap);
+  char* hi = P.ws + P.L.state + sizeof(SelState);
+  static_assert(offsetof(SelState, cand_cap) % 4 == 0, "word-aligned capacity");
+  fill_set({FillRange{(uint32_t*)lo, (uint64_t)(cap - lo) / 4, 0u, 0u},
+            FillRange{(uint32_t*)cap, 1u, P.L.cand_cap, 0u},
+            FillRange{(uint32_t*)(cap + 4), (uint64_t)(hi - cap - 4) / 4, 0u, 0u},
+            FillRange{(uint32_t*)d_counts, d_counts ? (uint64_t)nbins * 2 : 0u, 0u, 0u},
+            FillRange{(uint32_t*)outl, outl ? 4u : 0u, 0u, 0u}},
+           P.s);
 }
 
 template <int DT, bool VEC, bool NT>
@@ -1166,8 +1208,8 @@ int run_histogram(const tsa_cube* cube, const tsa_region* region, float lo, floa
   int st = prepare(cube, region, d_ws, ws_bytes, stream, &P, kBpcHist);
   if (st) return st;
   uint64_t* outl = d_outliers ? d_outliers : (uint64_t*)(P.ws + P.L.outl);
-  fill32(d_counts, (size_t)nbins * 2, 0u, P.s);
-  fill32(outl, 4, 0u, P.s);
+  fill_set({FillRange{(uint32_t*)d_counts, (uint64_t)nbins * 2, 0u, 0u}, FillRange{(uint32_t*)outl, 4u, 0u, 0u}},
+           P.s);
   const size_t budget = P.dev.lds_per_block < 65536 ? P.dev.lds_per_block : 65536;
   const uint32_t rs = rep_shift_for(nbins, budget);
   const size_t lds = (((size_t)nbins << rs) + kTrash) * 4;
@@ -1298,8 +1340,8 @@ int run_histogram_chunked(const tsa_cube* cube, float lo, float hi, int32_t nbin
   std::vector<Slab> slabs;
   if ((st = slabs_of(cube, chunk_voxels, P, &slabs))) return st;
   uint64_t* outl = d_outliers ? d_outliers : (uint64_t*)(P.ws + P.L.outl);
-  fill32(d_counts, (size_t)nbins * 2, 0u, P.s);
-  fill32(outl, 4, 0u, P.s);
+  fill_set({FillRange{(uint32_t*)d_counts, (uint64_t)nbins * 2, 0u, 0u}, FillRange{(uint32_t*)outl, 4u, 0u, 0u}},
+           P.s);
   const size_t budget = P.dev.lds_per_block < 65536 ? P.dev.lds_per_block : 65536;
   const uint32_t rs = rep_shift_for(nbins, budget);
   const size_t lds = (((size_t)nbins << rs) + kTrash) * 4;
@@ -1483,10 +1525,8 @@ static int enqueue_stats(const tsa_cube* cube, const tsa_region* region, int32_t
   // 16-bit counters: (nbins+1)/2 words + level-2 digits, plus ~10 KB of static LDS
   const size_t lds16 = ((((size_t)nbins + 1) / 2) + kBins2) * 4;
   if (wide && lds16 + 10240 > P.dev.lds_per_block) return TSA_ENOTSUP;
-  reset_select(P);
   uint64_t* outl = d_outliers ? d_outliers : (uint64_t*)(P.ws + P.L.outl);
-  fill32(d_counts, (size_t)nbins * 2, 0u, P.s);
-  fill32(outl, 4, 0u, P.s);
+  reset_select(P, d_counts, nbins, outl);
   Partial* parts = (Partial*)(P.ws + P.L.partials);
   SelState* stp = (SelState*)(P.ws + P.L.state);
   uint64_t* h1 = (uint64_t*)(P.ws + P.L.hist1);
@@ -1612,8 +1652,13 @@ int run_mad(const tsa_cube* cube, const tsa_region* region, double* d_out, void*
   uint64_t* h2 = (uint64_t*)(P.ws + P.L.hist2);
   uint64_t* h3 = (uint64_t*)(P.ws + P.L.hist3);
   uint32_t* cand = (uint32_t*)(P.ws + P.L.cand);
-  fill32(sb, sizeof(SelState) / 4, 0u, P.s);
-  fill32((char*)sb + offsetof(SelState, cand_cap), 1, P.L.cand_cap, P.s);
+  {
+    char* b = (char*)sb;
+    const size_t c = offsetof(SelState, cand_cap);
+    fill_set({FillRange{(uint32_t*)b, c / 4, 0u, 0u}, FillRange{(uint32_t*)(b + c), 1u, P.L.cand_cap, 0u},
+              FillRange{(uint32_t*)(b + c + 4), (sizeof(SelState) - c - 4) / 4, 0u, 0u}},
+             P.s);
+  }
   // 1. the lower median m
   const uint32_t rs = rep_shift_for(kBins1, 32768);
   TSA_TRACED("level1", P.s,
