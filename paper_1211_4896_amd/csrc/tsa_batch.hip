@@ -960,7 +960,7 @@ size_t batch_ws_bytes(const tsa_cube* cube, int32_t nbins, int32_t nq) {
   return batch_layout(nq).total;
 }
 
-static void bfill(void* p, size_t words, hipStream_t s);
+static void bfill3(void* p0, size_t n0, void* p1, size_t n1, void* p2, size_t n2, hipStream_t s);
 
 // launch choices of this thread's last enqueued batch (tsa_internal_batch_last_config)
 struct BatchConfig {
@@ -1198,9 +1198,7 @@ static int enqueue_region_batch(const tsa_cube* cube, const tsa_region* d_region
   const size_t lds2 = (((size_t)nbins << a.rshift) + kTrash + kBins2) * 4;
   size_t lds = lds1 > lds2 ? lds1 : lds2;
   if (lds < kEpLdsBytes) lds = kEpLdsBytes;
-  bfill(a.hdr, sizeof(BatchHdr) / 4, s);
-  bfill(a.digits, (size_t)kBins1 * nq, s);
-  bfill(d_hists, (size_t)nbins * nq * 2, s);
+  bfill3(a.hdr, sizeof(BatchHdr) / 4, a.digits, (size_t)kBins1 * nq, d_hists, (size_t)nbins * nq * 2, s);
   const int pb = (nq + 255) / 256;
   if (!a.tile_units) {
     if (cube->dtype == TSA_F32)
@@ -1229,16 +1227,26 @@ static int enqueue_region_batch(const tsa_cube* cube, const tsa_region* d_region
   return hipGetLastError() == hipSuccess ? TSA_OK : TSA_EDEVICE;
 }
 
-__global__ void k_bfill32(uint32_t* __restrict__ p, uint64_t n) {
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
-    p[i] = 0u;
+// The batch's clears (header, digit counters, output histograms) in one
+// launch: a small batch's time is mostly the gaps between its launches.
+struct BFill3 {
+  uint32_t* p[3];
+  uint64_t n[3];
+};
+__global__ void k_bfill32(BFill3 f) {
+  const uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (uint64_t)gridDim.x * blockDim.x;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    for (uint64_t i = i0; i < f.n[k]; i += stride) f.p[k][i] = 0u;
 }
 
-static void bfill(void* p, size_t words, hipStream_t s) {
-  if (!words) return;
-  int blocks = (int)((words + 255) / 256);
+static void bfill3(void* p0, size_t n0, void* p1, size_t n1, void* p2, size_t n2, hipStream_t s) {
+  const size_t most = n0 > n1 ? (n0 > n2 ? n0 : n2) : (n1 > n2 ? n1 : n2);
+  if (!most) return;
+  int blocks = (int)((most + 255) / 256);
   if (blocks > 2048) blocks = 2048;
-  TSA_TRACED("fill", s, hipLaunchKernelGGL(k_bfill32, dim3(blocks), dim3(256), 0, s, (uint32_t*)p, (uint64_t)words));
+  const BFill3 f{{(uint32_t*)p0, (uint32_t*)p1, (uint32_t*)p2}, {n0, n1, n2}};
+  TSA_TRACED("fill", s, hipLaunchKernelGGL(k_bfill32, dim3(blocks), dim3(256), 0, s, f));
 }
 
 }  // namespace tsa
