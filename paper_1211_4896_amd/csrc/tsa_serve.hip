@@ -41,6 +41,11 @@ struct RegionLane {
   void* d_ws = nullptr;
   size_t ws_bytes = 0;
   tsa_region* d_regions = nullptr;
+  // results then histograms in one allocation (and its pinned mirror), so one
+  // copy brings a batch's answers back
+  void* d_out = nullptr;
+  void* h_out = nullptr;
+  size_t hist_off = 0;  // bytes from the start to the histograms
   tsa_result* d_results = nullptr;
   uint64_t* d_hists = nullptr;
   tsa_region* h_regions = nullptr;
@@ -89,12 +94,18 @@ class GpuExecutor final : public sched::Executor {
       ok = ok && hipEventCreateWithFlags(&L.ev, hipEventDisableTiming) == hipSuccess;
       ok = ok && hipMalloc(&L.d_ws, bws) == hipSuccess;
       L.ws_bytes = bws;
+      L.hist_off = (sizeof(tsa_result) * nq + 255) & ~(size_t)255;
+      const size_t out_bytes = L.hist_off + sizeof(uint64_t) * nq * nb;
       ok = ok && hipMalloc((void**)&L.d_regions, sizeof(tsa_region) * nq) == hipSuccess;
-      ok = ok && hipMalloc((void**)&L.d_results, sizeof(tsa_result) * nq) == hipSuccess;
-      ok = ok && hipMalloc((void**)&L.d_hists, sizeof(uint64_t) * nq * nb) == hipSuccess;
+      ok = ok && hipMalloc(&L.d_out, out_bytes) == hipSuccess;
       ok = ok && hipHostMalloc((void**)&L.h_regions, sizeof(tsa_region) * nq, hipHostMallocDefault) == hipSuccess;
-      ok = ok && hipHostMalloc((void**)&L.h_results, sizeof(tsa_result) * nq, hipHostMallocDefault) == hipSuccess;
-      ok = ok && hipHostMalloc((void**)&L.h_hists, sizeof(uint64_t) * nq * nb, hipHostMallocDefault) == hipSuccess;
+      ok = ok && hipHostMalloc(&L.h_out, out_bytes, hipHostMallocDefault) == hipSuccess;
+      if (ok) {
+        L.d_results = (tsa_result*)L.d_out;
+        L.d_hists = (uint64_t*)((char*)L.d_out + L.hist_off);
+        L.h_results = (tsa_result*)L.h_out;
+        L.h_hists = (uint64_t*)((char*)L.h_out + L.hist_off);
+      }
     }
     FullLane& F = fl_;
     ok = ok && hipStreamCreateWithFlags(&F.stream, hipStreamNonBlocking) == hipSuccess;
@@ -173,10 +184,9 @@ class GpuExecutor final : public sched::Executor {
     if (st == TSA_OK)
       st = run_region_batch(&c.cube, L.d_regions, nq_pad, cfg_.region_nbins, L.d_results, L.d_hists, nullptr,
                             L.d_ws, L.ws_bytes, (tsa_stream_t)L.stream);
+    // one copy: the results (and the unused slots past nq) and the nq histograms
     if (st == TSA_OK &&
-        (hipMemcpyAsync(L.h_results, L.d_results, sizeof(tsa_result) * nq, hipMemcpyDeviceToHost, L.stream) !=
-             hipSuccess ||
-         hipMemcpyAsync(L.h_hists, L.d_hists, sizeof(uint64_t) * (size_t)nq * cfg_.region_nbins,
+        (hipMemcpyAsync(L.h_out, L.d_out, L.hist_off + sizeof(uint64_t) * (size_t)nq * cfg_.region_nbins,
                         hipMemcpyDeviceToHost, L.stream) != hipSuccess ||
          hipEventRecord(L.ev, L.stream) != hipSuccess))
       st = TSA_EDEVICE;
@@ -285,11 +295,9 @@ class GpuExecutor final : public sched::Executor {
       if (L.ev) (void)hipEventDestroy(L.ev);
       (void)hipFree(L.d_ws);
       (void)hipFree(L.d_regions);
-      (void)hipFree(L.d_results);
-      (void)hipFree(L.d_hists);
+      (void)hipFree(L.d_out);
       (void)hipHostFree(L.h_regions);
-      (void)hipHostFree(L.h_results);
-      (void)hipHostFree(L.h_hists);
+      (void)hipHostFree(L.h_out);
     }
     FullLane& F = fl_;
     if (F.stream) (void)hipStreamDestroy(F.stream);
