@@ -82,7 +82,11 @@ class Scheduler {
 
   // Finishes every queued and in-flight job, then ends the thread.
   void stop() {
-    stop_.store(true);
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      stop_.store(true);
+    }
+    arrive_cv_.notify_all();
     if (th_.joinable()) th_.join();
     std::lock_guard<std::mutex> g(mu_);
     for (Job* j : done_) delete j;
@@ -114,6 +118,7 @@ class Scheduler {
     }
     arrivals_.push_back(j);
     submitted_++;
+    arrive_cv_.notify_one();  // wakes a scheduler waiting with nothing in flight
     return TSA_OK;
   }
 
@@ -367,12 +372,20 @@ class Scheduler {
             adm_full_.empty())
           break;
       }
+      // Work in flight: poll its events without sleeping (a sleep here is added
+      // to every request's latency).  Nothing in flight and nothing to start:
+      // wait for an arrival (or stop), with a timeout as a safety net.
       if (did) {
         idle = 0;
-      } else if (++idle > 64) {
-        std::this_thread::sleep_for(std::chrono::microseconds(20));
-      } else {
+        continue;
+      }
+      bool busy = full_.busy;
+      for (const Lane& L : rl_) busy |= L.busy;
+      if (busy || ++idle <= 64) {
         std::this_thread::yield();
+      } else {
+        std::unique_lock<std::mutex> g(mu_);
+        arrive_cv_.wait_for(g, std::chrono::milliseconds(1), [this] { return !arrivals_.empty() || stop_.load(); });
       }
     }
   }
@@ -382,6 +395,7 @@ class Scheduler {
   const int lanes_;
   std::mutex mu_;
   std::condition_variable cv_;
+  std::condition_variable arrive_cv_;  // new arrivals and stop, for a scheduler with nothing in flight
   std::deque<Job*> arrivals_;            // guarded by mu_
   std::deque<Job*> done_;                // guarded by mu_
   uint64_t submitted_ = 0, finished_ = 0;  // guarded by mu_
