@@ -38,7 +38,13 @@ sys.path.insert(0, ROOT)
 # wait behind its kernels (region service p99 5.3 ms against 2.4 ms with eight
 # queues); a server process is configured with a queue per stream.  Read by
 # the HIP runtime when it starts, so it is set before anything touches the GPU.
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+try:
+    _queues = int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
+except ValueError:
+    _queues = 4
+if _queues < 8:
+    os.environ["GPU_MAX_HW_QUEUES"] = "8"
+
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 METRIC = "GVoxel/s + % HBM peak (hist, median); region queries/s batched vs plain, p99"
