@@ -32,20 +32,6 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# The serving run keeps three streams busy at once (two region lanes and the
-# full-scan lane) beside torch's own.  With HIP's default of four hardware
-# queues per process a region lane can land on the full-scan lane's queue and
-# wait behind its kernels (region service p99 5.3 ms against 2.4 ms with eight
-# queues); a server process is configured with a queue per stream.  Read by
-# the HIP runtime when it starts, so it is set before anything touches the GPU.
-try:
-    _queues = int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
-except ValueError:
-    _queues = 4
-if _queues < 8:
-    os.environ["GPU_MAX_HW_QUEUES"] = "8"
-
-
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 METRIC = "GVoxel/s + % HBM peak (hist, median); region queries/s batched vs plain, p99"
 KERNEL_SOURCES = ["tsa_device.hpp", "tsa_walk.hpp", "tsa_ops.hpp", "tsa_kernels.hip"]
@@ -232,7 +218,22 @@ def main():
     ap.add_argument("--no-minimap", action="store_true", help="skip the mini-map + k-sigma measurement")
     ap.add_argument("--no-spectrum", action="store_true", help="skip the spectrum-tool measurement")
     ap.add_argument("--no-c1", action="store_true", help="skip the 256^3 cache-resident case")
+    ap.add_argument("--hw-queues", type=int, default=8,
+                    help="raise the process's hardware queues to at least this many (0: leave the environment's)")
     args = ap.parse_args()
+    # The serving run keeps three streams busy at once (two region lanes and the
+    # full-scan lane) beside torch's own.  With HIP's default of four hardware
+    # queues per process a region lane can land on the full-scan lane's queue and
+    # wait behind its kernels (region service p99 5.3 ms against 2.4 ms with eight
+    # queues); a server process is configured with a queue per stream.  Read by
+    # the HIP runtime when it starts, so it is set before anything touches the GPU.
+    if args.hw_queues > 0:
+        try:
+            have = int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
+        except ValueError:
+            have = 4
+        if have < args.hw_queues:
+            os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this path does not shard)",
               file=sys.stderr)
