@@ -21,6 +21,13 @@
  *   - retires finished work by polling events and timestamps every stage.
  * Each request's result depends only on its own cube and box, never on what
  * else is in flight.
+ *
+ * Deployment: the server's streams (region_lanes + 1) overlap only if each
+ * has a hardware queue of its own; HIP gives a process four by default, which
+ * the caller's other streams share.  Start the process with
+ * GPU_MAX_HW_QUEUES of at least region_lanes + 1 plus the caller's busy
+ * streams (8 covers two lanes), or a region lane can wait behind a full-cube
+ * scan queued ahead of it.
  */
 #ifndef TSA_SERVE_H
 #define TSA_SERVE_H
