@@ -307,6 +307,11 @@ TSA_DEV uint32_t in_scalar_register(uint32_t v) {
 TSA_DEV void lds_add_at(uint32_t byte_addr, uint32_t v) {
   __hip_atomic_fetch_add((lds_word*)(uintptr_t)byte_addr, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
+// A workgroup barrier that orders LDS only: this wave's LDS operations
+// complete, then the barrier.  __syncthreads() also waits for every global
+// load in flight, which right after the cell's loads would hold each wave
+// until its last value arrived.
+TSA_DEV void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 // Histogram words of a cell: nbins << rshift replicas and the trash words,
 // rounded up to whole 16-byte groups.
@@ -407,7 +412,7 @@ __global__ __launch_bounds__(kMMBlock) __attribute__((amdgpu_waves_per_eu(EPT <=
       off += step + (carry ? wrap : 0u);
     }
   }
-  __syncthreads();  // counters cleared
+  lds_barrier();  // counters cleared (the loads still in flight)
   // moments, min/max keys and the first key digit.  The per-value steps are
   // written out here rather than through the shared accumulators: every step
   // sits under the value's own NaN test, so no select is needed, and the
